@@ -1,0 +1,249 @@
+"""Pins for the oracle's offline stage (oracle/schedule.py) against what the paper fixes.
+
+Each test names the passage it pins.  None of them retypes the oracle's own
+formula: they compare with printed values, an independent LP solution of the
+minimax problem, closed forms, or invariants of Theorems 1 and 2.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import schedule as S
+
+
+def _load_table(golden_dir, name):
+    rows = []
+    with open(os.path.join(golden_dir, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append([float(v) for v in line.split()])
+    return np.array(rows)
+
+
+def _lp_minimax(lo, hi, degree=5, n_grid=8000):
+    """min_p max_{x in grid} |1 - p(x)| over odd p of the given degree, as a
+    linear programme (scipy HiGHS): variables (coeffs, E), minimise E subject to
+    -E <= 1 - p(x_i) <= E.  Independent of the Remez exchange."""
+    from scipy.optimize import linprog
+    x = np.linspace(lo, hi, n_grid)
+    powers = np.arange(1, degree + 1, 2)
+    V = x[:, None] ** powers[None, :]
+    k = len(powers)
+    c = np.zeros(k + 1)
+    c[-1] = 1.0
+    A_ub = np.block([[-V, -np.ones((n_grid, 1))], [V, -np.ones((n_grid, 1))]])
+    b_ub = np.concatenate([-np.ones(n_grid), np.ones(n_grid)])
+    res = linprog(c, A_ub=A_ub, b_ub=b_ub, bounds=[(None, None)] * (k + 1), method="highs")
+    assert res.success
+    return res.x[:k], res.x[-1]
+
+
+def test_paper_table_reproduced(golden_dir):
+    """Appendix A.1 prints the l = 1e-3 schedule (before the safety factor)."""
+    paper = _load_table(golden_dir, "paper_coeffs_ell1e-3.txt")
+    sch = S.greedy_schedule(1e-3, 8, safety=1.0)
+    got = sch.abc_unsafe
+    rel = np.abs(got - paper) / np.abs(paper)
+    assert rel[:6].max() <= 1e-13, rel[:6]
+    # step 7 is designed on [0.99881, 1.00119]; the 4x4 system there has
+    # condition number ~2e6, so two float64 solves differ at ~1e-10
+    assert rel[6].max() <= 2e-10, rel[6]
+    assert np.array_equal(got[7], paper[7])
+    assert sch.degenerate.tolist() == [False] * 7 + [True]
+
+
+def test_float64_remez_within_conditioning_of_exact():
+    """The float64 exchange agrees with a 50-digit one to within the 4x4
+    system's conditioning (Appendix E notes ill-conditioning as l -> u)."""
+    sch = S.greedy_schedule(1e-3, 7, safety=1.0)
+    for t in range(7):
+        lo = max(sch.ell[t], S.CUSHION * sch.u[t])
+        r = S.remez_quintic(lo, sch.u[t])
+        a, b, c, E = S.remez_quintic_mp(lo, sch.u[t])
+        pts = np.array([lo, 0.75 * lo + 0.25 * sch.u[t], 0.25 * lo + 0.75 * sch.u[t], sch.u[t]])
+        cond = np.linalg.cond(np.stack([pts, pts ** 3, pts ** 5, [1, -1, 1, -1]], 1))
+        bound = 50 * cond * np.finfo(float).eps
+        for got, ref in zip((r.a, r.b, r.c), (a, b, c)):
+            assert abs(got - float(ref)) <= bound * abs(float(ref)), (t, got, float(ref), bound)
+
+
+def test_paper_table_lower_bounds(golden_dir):
+    """Theorem 1, eq. (newbounds): l_{t+1} = p_t(l_t), u_{t+1} = 2 - l_{t+1}.
+    Running the recursion on the printed coefficients gives the same bounds."""
+    paper = _load_table(golden_dir, "paper_coeffs_ell1e-3.txt")
+    sch = S.greedy_schedule(1e-3, 7, safety=1.0)
+    l = 1e-3
+    for t in range(7):
+        a, b, c = paper[t]
+        l = a * l + b * l ** 3 + c * l ** 5
+        assert abs(l - sch.ell[t + 1]) <= 1e-9 * max(1.0, l), (t, l, sch.ell[t + 1])
+
+
+def test_remez_equioscillates():
+    """Lemma (equioscillation), d = 5: q + 2 = 4 points with alternating sign
+    where |1 - p| attains its maximum on [l, u]."""
+    for lo, hi in [(1e-3, 1.0), (0.03, 1.0), (0.2, 1.0), (0.5, 1.3), (0.9, 1.1)]:
+        r = S.remez_quintic(lo, hi)
+        pts = np.array(r.points)
+        err = 1.0 - S.eval_odd_quintic((r.a, r.b, r.c), pts)
+        E = abs(r.E)
+        assert np.allclose(np.abs(err), E, rtol=1e-10, atol=1e-14)
+        assert np.all(np.sign(err[:-1]) == -np.sign(err[1:]))
+        grid = np.linspace(lo, hi, 200001)
+        emax = np.max(np.abs(1.0 - S.eval_odd_quintic((r.a, r.b, r.c), grid)))
+        assert emax <= E * (1 + 1e-9) + 1e-15
+        assert lo < pts[1] < pts[2] < hi
+
+
+def test_remez_matches_lp_minimax():
+    """The minimax error found by the exchange equals the optimum of the
+    discretised minimax problem solved as a linear programme."""
+    for lo, hi in [(1e-3, 1.0), (S.CUSHION, 1.0), (0.1, 1.0), (0.4, 1.2)]:
+        r = S.remez_quintic(lo, hi)
+        coef, E_lp = _lp_minimax(lo, hi, 5)
+        assert abs(abs(r.E) - E_lp) <= 1e-7 * max(1.0, E_lp) + 2e-8
+        assert np.allclose(coef, [r.a, r.b, r.c], rtol=1e-4, atol=1e-4)
+
+
+def test_remez_iteration_count():
+    """Appendix E: the exchange never needed more than five iterations."""
+    sch = S.greedy_schedule(1e-3, 10, safety=1.0)
+    assert sch.remez_iters.max() <= 5
+
+
+def test_cushion_is_tenth_ratio_rule():
+    """Appendix F motivates the cushion by a ratio-1/10 rule.  The listing's
+    constant is the r at which the minimax quintic on [r, 1] has error 9/11,
+    i.e. maps [r, 1] onto [2/11, 20/11], an interval of ratio 1/10."""
+    r = S.remez_quintic(S.CUSHION, 1.0)
+    assert abs(abs(r.E) - 9.0 / 11.0) <= 1e-12
+    lo_img = 1 - abs(r.E)
+    hi_img = 1 + abs(r.E)
+    assert abs(lo_img / hi_img - 0.1) <= 1e-12
+
+
+def test_theorem1_composite_error_pure_greedy():
+    """Theorem 1, eq. (optimal): max_{x in [l,u]} |1 - phi_T(x)| = 1 - l_{T+1},
+    and the composite equioscillates at 3^T + 1 points (degree 5^T odd
+    polynomial whose error alternates through every level crossing)."""
+    for T in (1, 2, 3):
+        sch = S.greedy_schedule(0.03, T, cushion=0.0, safety=1.0)
+        x = np.linspace(0.03, 1.0, 400001)
+        err = 1.0 - S.composite(sch.abc, x)
+        bound = sch.err_bound
+        assert abs(np.max(np.abs(err)) - bound) <= 1e-9
+        # count alternation points: local extrema of err that reach |err| ~ bound
+        hits = np.abs(np.abs(err) - bound) <= 1e-6
+        # group consecutive hits into points
+        idx = np.flatnonzero(hits)
+        groups = np.split(idx, np.flatnonzero(np.diff(idx) > 1) + 1)
+        signs = [np.sign(err[g[len(g) // 2]]) for g in groups if len(g)]
+        assert len(signs) == 3 ** T + 1, (T, len(signs))
+        assert all(signs[i] == -signs[i + 1] for i in range(len(signs) - 1))
+
+
+def test_theorem1_recentred_error_at_endpoints():
+    """With cushioning and re-centring, each p_t maps [l_t, u_t] into
+    [l_{t+1}, 2 - l_{t+1}], so the composite's error is 1 - l_{T+1}, attained at l."""
+    for T in (3, 5, 6):
+        sch = S.greedy_schedule(1e-3, T, safety=1.0)
+        x = np.geomspace(1e-3, 1.0, 400001)
+        err = 1.0 - S.composite(sch.abc, x)
+        assert abs(np.max(np.abs(err)) - sch.err_bound) <= 1e-9 * max(1, sch.err_bound) + 1e-12
+        assert abs(err[0] - sch.err_bound) <= 1e-12
+
+
+def test_theorem2_bound():
+    """Theorem 2: ||polar(M) - X_T|| <= |1 - l^2|^{(q+1)^T}, q = 2 for d = 5."""
+    for ell in (1e-3, 0.03, 0.2):
+        for T in range(1, 7):
+            sch = S.greedy_schedule(ell, T, cushion=0.0, safety=1.0)
+            x = np.geomspace(ell, 1.0, 100001)
+            emax = np.max(np.abs(1 - S.composite(sch.abc, x)))
+            assert emax <= (1 - ell ** 2) ** (3 ** T) + 1e-12
+
+
+def test_degree3_closed_form_equioscillates():
+    """Appendix E, eq. (deg3_solution): p = beta p_NS(alpha x) satisfies
+    p(l) = p(u) = 1 - E and p(1/alpha) = 1 + E, E = beta - 1; and it is the LP optimum."""
+    for lo, hi in [(1e-3, 1.0), (0.1, 1.0), (0.5, 2.0)]:
+        a, b, E = S.cubic_closed_form(lo, hi)
+        p = lambda x: a * x + b * x ** 3
+        xm = math.sqrt(-a / (3 * b))
+        assert abs(p(lo) - (1 - E)) <= 1e-13
+        assert abs(p(hi) - (1 - E)) <= 1e-13
+        assert abs(p(xm) - (1 + E)) <= 1e-13
+        coef, E_lp = _lp_minimax(lo, hi, 3)
+        assert abs(E - E_lp) <= 1e-7
+
+
+def test_safety_fixed_point():
+    """Appendix F: with p(x/1.01) the singular values converge to 0.999998."""
+    p = lambda x: S.eval_odd_quintic(S.NS5, x / 1.01)
+    x = 1.0
+    for _ in range(200):
+        x = float(p(x))
+    assert abs(x - 0.999998) <= 5e-7
+    assert abs(float(p(x)) - x) <= 1e-15
+
+
+def test_safety_and_degenerate_handling():
+    """Appendix A.1: the safety transform (a/1.01, b/1.01^3, c/1.01^5) is applied
+    to every non-Newton-Schulz entry; the NS5 entry and its repeats are exempt."""
+    sch = S.greedy_schedule(1e-3, 10)
+    for t in range(10):
+        a, b, c = sch.abc_unsafe[t]
+        if sch.degenerate[t]:
+            assert tuple(sch.abc[t]) == S.NS5
+        else:
+            assert np.allclose(sch.abc[t], [a / 1.01, b / 1.01 ** 3, c / 1.01 ** 5], rtol=1e-15)
+    assert sch.degenerate[7:].all()
+    # the recurrence after step 8 is at the fixed point u = 2 - l ~ 1
+    assert abs(sch.ell[-1] - 1.0) <= 1e-15
+
+
+def test_small_singular_value_suppression():
+    """Appendix (small singular values): five steps with l = 1e-3 map singular
+    values >= 1e-3 close to 1 and those below 1e-4 close to 0."""
+    sch = S.greedy_schedule(1e-3, 5)
+    hi = S.composite(sch.abc, np.geomspace(1e-3, 1.0, 10001))
+    lo = S.composite(sch.abc, np.geomspace(1e-8, 1e-4, 1001))
+    assert np.all(np.abs(1 - hi) <= 0.16)
+    assert np.all(lo <= 0.1)
+
+
+def test_figure3_qualitative(golden_dir):
+    """Section 4.1 (Figure 3 left), scalar form on sigma log-spaced in [1e-6, 1]:
+    Newton-Schulz (degree 5) makes almost no progress in 17 iterations; Jordan's
+    quintic plateaus near 0.3; Polar Express with l = sigma_min reaches high
+    accuracy by iteration 11 and dominates both at every iteration."""
+    x = np.geomspace(1e-6, 1.0, 20001)
+    jordan = tuple(_load_table(golden_dir, "jordan_quintic.txt")[0])
+
+    def err_curve(abc_list):
+        y = x.copy()
+        out = []
+        for abc in abc_list:
+            y = S.eval_odd_quintic(abc, y)
+            out.append(np.max(np.abs(1 - y)))
+        return np.array(out)
+
+    ns = err_curve([S.NS5] * 17)
+    jo = err_curve([jordan] * 20)
+    pe = err_curve(S.greedy_schedule(1e-6, 20, cushion=0.0, safety=1.0).abc)
+    assert ns[16] > 0.9
+    assert 0.2 < jo[10] < 0.4 and 0.2 < jo[19] < 0.4
+    assert pe[10] < 1e-2
+    assert np.all(pe[:17] <= ns[:17] + 1e-12)
+    assert np.all(pe[10:] < jo[10:])
+
+
+def test_extend_repeats_last():
+    """Appendix A.1: steps past the table repeat the last triple."""
+    tab = np.arange(6.0).reshape(2, 3)
+    ext = S.extend_schedule(tab, 5)
+    assert ext.shape == (5, 3)
+    assert np.array_equal(ext[1:], np.repeat(tab[1:], 4, axis=0))
