@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""Polar Express throughput on one MI355X.
+
+One step = one pass of the whole method (norm + T polynomial steps) over every
+matrix of the workload, through a plan (grouped launches captured as a
+hipGraph).  Inputs are synthetic, seeded, resident in HBM before timing.
+
+Workloads:
+  wide-batch        32-layer 4096-wide model: per layer four 4096x4096 and three
+                    4096x14336 bf16 matrices (224), sigma_i = 1/i, Haar singular
+                    vectors, T = 5                                   (default)
+  gpt-small-batch   12 layers x {768x2304, 768x768, 768x3072, 3072x768} (48), sigma_i = 1/i
+  single-4096x1024  one 4096x1024 bf16 matrix, log-uniform spectrum
+
+Metric: algorithmic TFLOP/s = sum over matrices and steps of (3 s^2 L + s^3)
+(s = min(m,n), L = max(m,n): Gram s^2 L, A^2 s^3 on the symmetric half, B X
+2 s^2 L) divided by the wall time of the step.
+
+Prints ONE JSON line (rank 0, N = 1).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP8_TFLOPS = 5000.0
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algo_flops(shapes, T):
+    tot = 0.0
+    for m, n in shapes:
+        s, L = min(m, n), max(m, n)
+        tot += 3.0 * s * s * L + float(s) ** 3
+    return tot * T
+
+
+def update_flops(shapes):
+    return sum(2.0 * min(m, n) ** 2 * max(m, n) for m, n in shapes)
+
+
+def make_workload(name, torch, device):
+    import synth
+    if name == "wide-batch":
+        mats, templates = synth.torch_layer_batch(32, seed=1004, device=device)
+        Gs = [m[0] for m in mats]
+        meta = dict(mats=mats, templates=templates)
+        return Gs, 5, meta
+    if name == "gpt-small-batch":
+        mats, templates = synth.torch_layer_batch(12, seed=1003, device=device,
+                                                  shapes=synth.GPT_SMALL_SHAPES)
+        return [m[0] for m in mats], 5, dict(mats=mats, templates=templates)
+    if name == "single-4096x1024":
+        S = synth.loguniform(1002)
+        G = torch.from_numpy(S.G.astype("float32")).to(torch.bfloat16).to(device)
+        return [G], 5, dict(synth=S)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def polar_factor(meta, idx, torch):
+    """U' V^T of matrix idx (known by construction)."""
+    if "mats" in meta:
+        G, perm, signs, j = meta["mats"][idx]
+        U, sig, V = meta["templates"][j]
+        return (U[:, perm] * signs) @ V.T
+    S = meta["synth"]
+    return torch.from_numpy(S.polar()).float().cuda()
+
+
+def spec_norm_gpu(D, torch, iters=60):
+    """||D||_2 by power iteration on D^T D (measurement only)."""
+    g = torch.Generator(device=D.device)
+    g.manual_seed(0)
+    v = torch.randn(D.shape[1], 1, device=D.device, generator=g, dtype=torch.float32)
+    v /= v.norm()
+    lam = torch.zeros((), device=D.device)
+    for _ in range(iters):
+        w = D.T @ (D @ v)
+        lam = w.norm()
+        v = w / lam
+    return float(lam.sqrt())
+
+
+def cpu_baseline(G_cpu64, abc, T):
+    """The FP64 oracle on the host cores, on one matrix of the workload."""
+    import numpy as np
+    from oracle import iteration as OI
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    t0 = time.perf_counter()
+    OI.polar_express(G_cpu64, abc)
+    dt = time.perf_counter() - t0
+    m, n = G_cpu64.shape
+    fl = algo_flops([(m, n)], T)
+    return dict(value=fl / dt / 1e12, unit="TFLOP/s", cores=int(cores), kind="oracle",
+                sample=f"1 of the workload's matrices ({m}x{n}), T={T}, FP64 NumPy, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="wide-batch",
+                    choices=["wide-batch", "gpt-small-batch", "single-4096x1024"])
+    ap.add_argument("--compute", default="bf16", choices=["bf16", "fp8", "f32"])
+    ap.add_argument("--fp8-steps", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--phase-reps", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(matrices would be sharded across GPUs with no exchange during the iteration)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2505_16932_amd as pe
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    dev = torch.device("cuda:0")
+    pe.lib()
+    log(f"[bench] generating workload {args.workload}")
+    t0 = time.perf_counter()
+    Gs, T, meta = make_workload(args.workload, torch, dev)
+    torch.cuda.synchronize()
+    log(f"[bench] {len(Gs)} matrices ready in {time.perf_counter() - t0:.1f} s")
+    shapes = [tuple(G.shape) for G in Gs]
+    abc = pe.coeffs(1e-3, T).abc
+    stream = torch.cuda.current_stream()
+
+    plan = pe.Plan(Gs, T=T, abc=abc, compute=args.compute, fp8_steps=args.fp8_steps)
+    log(f"[bench] plan ready, workspace {plan.ws_bytes / 2**30:.1f} GiB")
+    for _ in range(args.warmup):
+        plan.launch(graph=True)
+    torch.cuda.synchronize()
+    log("[bench] warmup done")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.launch(graph=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = ev0.elapsed_time(ev1) / args.steps
+    flops = algo_flops(shapes, T)
+    tflops = flops / (ms * 1e-3) / 1e12
+    log(f"[bench] {ms:.3f} ms/step, {tflops:.1f} TFLOP/s (wall {wall / args.steps * 1e3:.3f} ms/step)")
+
+    # dominant kernel: the update X = aX + BX of a middle step, timed alone on
+    # the stream it is launched on
+    step = 1 if T > 2 else 0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    plan.launch_phase(step, 3)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.phase_reps):
+        plan.launch_phase(step, 3)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    upd_ms = e0.elapsed_time(e1) / args.phase_reps
+    upd_tf = update_flops(shapes) / (upd_ms * 1e-3) / 1e12
+    log(f"[bench] update kernel {upd_ms:.3f} ms, {upd_tf:.1f} TFLOP/s")
+    # restore a valid result after the diagnostic launches
+    plan.launch(graph=True)
+    torch.cuda.synchronize()
+
+    extra = {}
+    if not args.no_error:
+        errs = []
+        for idx in sorted(set([0, min(4, len(Gs) - 1)])):
+            P = polar_factor(meta, idx, torch).float()
+            errs.append(spec_norm_gpu(plan.outs[idx].float() - P, torch))
+        extra["polar_err_sampled"] = [round(e, 5) for e in errs]
+        log(f"[bench] ||X - UV^T||_2 on sampled matrices: {errs}")
+
+    if not args.no_plain:
+        # plain single-matrix path: one eager pe_polar per matrix, same schedule
+        outs = [torch.empty_like(G) for G in Gs]
+        for G, X in zip(Gs[:2], outs[:2]):
+            pe.polar(G, T=T, abc=abc, compute=args.compute, out=X, fp8_steps=args.fp8_steps)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for G, X in zip(Gs, outs):
+            pe.polar(G, T=T, abc=abc, compute=args.compute, out=X, fp8_steps=args.fp8_steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        plain_ms = e0.elapsed_time(e1)
+        extra["plain_single_matrix"] = dict(ms_per_step=round(plain_ms, 3),
+                                            tflops=round(flops / (plain_ms * 1e-3) / 1e12, 2))
+        log(f"[bench] plain path {plain_ms:.3f} ms/step")
+        del outs
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        idx = len(Gs) - 1
+        G64 = Gs[idx].to(torch.float64).cpu().numpy()
+        log(f"[bench] cpu oracle on {G64.shape}")
+        cpu = cpu_baseline(G64, abc, T)
+        log(f"[bench] cpu oracle {cpu['value']:.4f} TFLOP/s")
+
+    peak = PEAK_BF16_TFLOPS
+    out = {
+        "metric": "polar TFLOP/s & % MFMA peak at fixed ||X-UV^T||_2, batched vs plain bf16",
+        "value": round(tflops, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"bf16": "bf16", "fp8": "fp8e4m3+bf16", "f32": "f32"}[args.compute],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "matrices": len(Gs), "T": T, "ell": 1e-3,
+                   "compute": args.compute, "fp8_steps": args.fp8_steps,
+                   "shapes": sorted(set(shapes))},
+        "pct_bf16_peak": round(100.0 * tflops / peak, 2),
+        "matrices_per_s": round(len(Gs) / (ms * 1e-3), 2),
+        "roofline": {"bound": "mfma", "achieved": round(upd_tf, 2), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(upd_tf / peak, 4), "traffic": None,
+                     "kernel": "gemm_kernel<bf16, update> (X = aX + BX)",
+                     "avg_ms": round(upd_ms, 4)},
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

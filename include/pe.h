@@ -1,0 +1,167 @@
+/*
+ * pe.h -- C ABI of the MI355X (gfx950) Polar Express library.
+ *
+ * Polar Express (Amsel, Persson, Musco, Gower, arXiv 2505.16932) approximates
+ * polar(M) = U V^T (eq. matrixsign) by a composition of odd quintics
+ * p_t(x) = a_t x + b_t x^3 + c_t x^5 chosen greedily to be minimax optimal on
+ * [l_t, u_t] (Theorem 1), applied to a normalised input (Section 3.5,
+ * Algorithm 1 and the Appendix A.1 listing):
+ *     X_0 = G / (1.01 ||G||_F + 1e-7)
+ *     for t = 1..T:  A = X X^T;  B = b_t A + c_t A^2;  X = a_t X + B X
+ * with X oriented so that the Gram matrix A is formed on the smaller side.
+ *
+ * Conventions for every entry point:
+ *  - Matrices are dense row-major: element (i, j) of an m x n matrix with
+ *    leading dimension ld sits at base[i * ld + j], ld >= n.
+ *  - G, X and the workspace are DEVICE pointers owned by the caller (for
+ *    example PyTorch tensors).  The library never allocates device memory on
+ *    the compute path; it never frees caller memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    All GPU entry points are asynchronous on that stream unless stated.
+ *  - No exceptions cross the ABI; every entry point returns a pe_status and
+ *    pe_status_string() describes it.  Device faults surface at the caller's
+ *    next synchronisation.
+ *  - X must not alias G or the workspace.  Concurrent calls on different
+ *    streams must use different workspaces.
+ */
+#ifndef PE_H
+#define PE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PE_OK = 0,
+  PE_EINVAL = 1,        /* invalid argument (null pointer, bad size, bad ld, bad l or T) */
+  PE_EUNSUPPORTED = 2,  /* valid request this build does not implement */
+  PE_ENOCONV = 3,       /* the Remez exchange did not converge */
+  PE_EWORKSPACE = 4,    /* workspace missing, too small or misaligned (256 B) */
+  PE_EHIP = 5           /* a HIP runtime call failed (message: pe_last_error) */
+} pe_status;
+
+/* Storage type of G and X. */
+typedef enum { PE_F32 = 0, PE_BF16 = 1 } pe_dtype;
+
+/* Arithmetic of the online stage.
+ *  PE_COMPUTE_F32 : FP32 operands on FP32 MFMA, FP32 accumulation.
+ *  PE_COMPUTE_BF16: FP32 master iterate; bf16 MFMA operands (X, A, B);
+ *                   FP32 accumulation and FP32 epilogues.
+ *  PE_COMPUTE_FP8 : as BF16, but in the first `fp8_steps` steps the two
+ *                   Gram-side products (X X^T and A A^T) take OCP e4m3
+ *                   operands with one per-tensor scale each (amax -> 448),
+ *                   FP32 accumulation; the remaining steps are bf16. */
+typedef enum { PE_COMPUTE_F32 = 0, PE_COMPUTE_BF16 = 1, PE_COMPUTE_FP8 = 2 } pe_compute;
+
+/* ---------------------------------------------------------------------------
+ * Offline stage: the coefficient schedule (host, FP64, synchronous,
+ * thread-safe, no GPU).
+ *
+ * Theorem 1 (greedy is optimal) with the degree-5 Remez exchange of
+ * Appendix E (Algorithm 3, eq. linearsystem) and the finite-precision changes
+ * of Section 3.4 / Appendix F, as the offline generator of Appendix A.2 does:
+ *   u_1 = 1, l_1 = ell;  for t = 1..T:
+ *     p_t = minimax odd quintic for 1 on [max(l_t, cushion*u_t), u_t]
+ *           (Newton-Schulz (15/8, -10/8, 3/8) once max(l_t,...)/u_t >= 1-5e-6);
+ *     p_t <- p_t * 2 / (p_t(l_t) + p_t(u_t))          (re-centring)
+ *     l_{t+1} = p_t(l_t),  u_{t+1} = 2 - l_{t+1}      (eq. newbounds)
+ *   then every non-Newton-Schulz step is replaced by p_t(x / safety).
+ * cushion < 0 selects Algorithm 1's rule [max(l_t, u_t/10), u_t] (no re-centring).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double cushion;          /* default 0.02407327424182761; 0 = pure greedy */
+  double safety;           /* default 1.01; 1.0 = off */
+  int32_t safety_on_last;  /* default 1; 0 = leave the last step unscaled */
+} pe_coeff_opts;
+
+/* Fill *opts with the defaults above. */
+void pe_coeff_opts_default(pe_coeff_opts* opts);
+
+/* ell in (0, 1), 1 <= T <= 64.
+ *   abc       out, host, 3*T doubles: (a_t, b_t, c_t) for t = 1..T.
+ *   bounds    out, host, nullable, 2*(T+1) doubles: l_1, u_1, ..., l_{T+1}, u_{T+1}.
+ *   err_bound out, host, nullable: 1 - l_{T+1}, the worst-case spectral error
+ *             on [ell, 1] of the composite before the safety factor (eq. optimal).
+ *   iters     out, host, nullable, T ints: Remez exchanges per step (0 = NS5).
+ * Returns PE_EINVAL on bad arguments, PE_ENOCONV if an exchange fails. */
+pe_status pe_coeffs(double ell, int32_t T, const pe_coeff_opts* opts, double* abc,
+                    double* bounds, double* err_bound, int32_t* iters);
+
+/* ---------------------------------------------------------------------------
+ * Online stage.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const void* G;       /* device, m x n, leading dimension ldg (elements), dtype g_dtype */
+  void* X;             /* device, m x n output, leading dimension ldx, dtype x_dtype */
+  int64_t m, n;        /* m, n >= 0; m = 0 or n = 0 is a no-op */
+  int64_t ldg, ldx;    /* >= n */
+  int32_t g_dtype;     /* pe_dtype */
+  int32_t x_dtype;     /* pe_dtype */
+} pe_matrix;
+
+typedef struct {
+  int32_t T;           /* number of steps, 1..64 */
+  const double* abc;   /* host, 3*T doubles (for example from pe_coeffs) */
+  int32_t compute;     /* pe_compute */
+  int32_t fp8_steps;   /* PE_COMPUTE_FP8 only: leading steps in e4m3 (0..T-1) */
+  int32_t norm_mode;   /* 0: X_0 = G/(1.01||G||_F + 1e-7) (Appendix A.1 listing);
+                          1: X_0 = G/(||G||_F + 1e-2) (Algorithm 1) */
+  int32_t tile;        /* 0 = library choice (autotuned table if loaded), else a
+                          tile id from pe_tile_count()/pe_tile_name() */
+} pe_opts;
+
+/* Bytes of device workspace needed by pe_polar / pe_polar_batched / a plan
+ * for these matrices and options (0 on invalid input).  Workspace must be
+ * 256-byte aligned; its contents need no initialisation. */
+size_t pe_workspace_size(int32_t count, const pe_matrix* mats, const pe_opts* opts);
+
+/* One matrix: X = PolarExpress(G).  Asynchronous on `stream`. */
+pe_status pe_polar(const pe_matrix* mat, const pe_opts* opts, void* ws, size_t ws_bytes,
+                   void* stream);
+
+/* A list of matrices of uneven shapes in grouped launches: each phase (norm,
+ * Gram, A^2 + combine, update) is one persistent launch over the tiles of all
+ * matrices.  The tile tables are written into the workspace by small kernels
+ * on `stream` (no host synchronisation); a plan does that once for repeated
+ * calls on the same matrices. */
+pe_status pe_polar_batched(int32_t count, const pe_matrix* mats, const pe_opts* opts,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* Plans: the grouped launches of pe_polar_batched with the tile tables built
+ * and uploaded once and the whole T-step sequence captured as a hipGraph on
+ * the first launch.  The plan keeps the pointers it was created with; the
+ * caller keeps G, X and ws alive and unchanged in shape while it exists. */
+typedef struct pe_plan pe_plan;
+pe_status pe_plan_create(int32_t count, const pe_matrix* mats, const pe_opts* opts, void* ws,
+                         size_t ws_bytes, void* stream, pe_plan** plan);
+/* use_graph = 1: replay the captured graph; 0: launch the kernels eagerly. */
+pe_status pe_plan_launch(pe_plan* plan, void* stream, int32_t use_graph);
+pe_status pe_plan_destroy(pe_plan* plan);
+
+/* Diagnostic: enqueue one phase of one step of a plan on `stream`, eagerly,
+ * so that a profiler or timer can measure that kernel alone.  phase: 0 = norm
+ * and copies of X_0, 1 = Gram product (with its split-K reduction),
+ * 2 = A^2 + combine (with its reduction), 3 = update X = aX + BX.  The phase
+ * reads whatever the plan's buffers hold (run pe_plan_launch first); the
+ * buffers are left in an unspecified state, the caller's X untouched unless
+ * step = T-1 and phase = 3.  PE_EINVAL for a bad step or phase. */
+pe_status pe_plan_launch_phase(pe_plan* plan, int32_t step, int32_t phase, void* stream);
+
+/* Tile configurations compiled into the library and the autotuned table.
+ * pe_tile_table_load reads a text table "<shape-class> <tile-id>" per line
+ * (written by the autotuner); it replaces the built-in choices. */
+int32_t pe_tile_count(void);
+const char* pe_tile_name(int32_t tile_id);
+pe_status pe_tile_table_load(const char* path);
+
+const char* pe_status_string(pe_status st);
+/* Text of the last HIP error seen by this thread (empty if none). */
+const char* pe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PE_H */

@@ -1,0 +1,291 @@
+"""Python binding of the gfx950 Polar Express library (libpe.so, C ABI in include/pe.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels (or, for the coefficient schedule, its host FP64 code).  PyTorch
+supplies device memory (inputs, outputs, workspace) and the current stream.
+
+    import paper_2505_16932_amd as pe
+    abc = pe.coeffs(1e-3, 5).abc                       # offline stage, FP64
+    X = pe.polar(G, T=5)                               # one matrix
+    Xs = pe.polar_batched([G1, G2, G3], T=5)           # grouped launches
+    plan = pe.Plan(Gs, T=5); plan.launch(graph=True)   # tables once + hipGraph
+
+The library file must have been built (``paper_2505_16932_amd.build``); there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = ["coeffs", "polar", "polar_batched", "Plan", "workspace_size", "lib", "PEError",
+           "COMPUTE", "LIB_PATH"]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpe.so")
+
+PE_F32, PE_BF16 = 0, 1
+COMPUTE = {"f32": 0, "bf16": 1, "fp8": 2}
+STATUS = {0: "PE_OK", 1: "PE_EINVAL", 2: "PE_EUNSUPPORTED", 3: "PE_ENOCONV",
+          4: "PE_EWORKSPACE", 5: "PE_EHIP"}
+
+
+class PEError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        msg = f"{where}: {STATUS.get(status, status)}"
+        if detail:
+            msg += f" ({detail})"
+        super().__init__(msg)
+
+
+class CoeffOpts(ctypes.Structure):
+    _fields_ = [("cushion", ctypes.c_double), ("safety", ctypes.c_double),
+                ("safety_on_last", ctypes.c_int32)]
+
+
+class Matrix(ctypes.Structure):
+    _fields_ = [("G", ctypes.c_void_p), ("X", ctypes.c_void_p), ("m", ctypes.c_int64),
+                ("n", ctypes.c_int64), ("ldg", ctypes.c_int64), ("ldx", ctypes.c_int64),
+                ("g_dtype", ctypes.c_int32), ("x_dtype", ctypes.c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_int32), ("abc", ctypes.POINTER(ctypes.c_double)),
+                ("compute", ctypes.c_int32), ("fp8_steps", ctypes.c_int32),
+                ("norm_mode", ctypes.c_int32), ("tile", ctypes.c_int32)]
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libpe.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2505_16932_amd.build` (no fallback path exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.pe_coeffs.restype = ctypes.c_int
+        L.pe_coeffs.argtypes = [ctypes.c_double, ctypes.c_int32, ctypes.POINTER(CoeffOpts),
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+        L.pe_coeff_opts_default.restype = None
+        L.pe_coeff_opts_default.argtypes = [ctypes.POINTER(CoeffOpts)]
+        L.pe_workspace_size.restype = ctypes.c_size_t
+        L.pe_workspace_size.argtypes = [ctypes.c_int32, ctypes.POINTER(Matrix), ctypes.POINTER(Opts)]
+        L.pe_polar.restype = ctypes.c_int
+        L.pe_polar.argtypes = [ctypes.POINTER(Matrix), ctypes.POINTER(Opts), ctypes.c_void_p,
+                               ctypes.c_size_t, ctypes.c_void_p]
+        L.pe_polar_batched.restype = ctypes.c_int
+        L.pe_polar_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(Matrix), ctypes.POINTER(Opts),
+                                       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.pe_plan_create.restype = ctypes.c_int
+        L.pe_plan_create.argtypes = [ctypes.c_int32, ctypes.POINTER(Matrix), ctypes.POINTER(Opts),
+                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                     ctypes.POINTER(ctypes.c_void_p)]
+        L.pe_plan_launch.restype = ctypes.c_int
+        L.pe_plan_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+        L.pe_plan_launch_phase.restype = ctypes.c_int
+        L.pe_plan_launch_phase.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_void_p]
+        L.pe_plan_destroy.restype = ctypes.c_int
+        L.pe_plan_destroy.argtypes = [ctypes.c_void_p]
+        L.pe_tile_count.restype = ctypes.c_int32
+        L.pe_tile_name.restype = ctypes.c_char_p
+        L.pe_tile_name.argtypes = [ctypes.c_int32]
+        L.pe_tile_table_load.restype = ctypes.c_int
+        L.pe_tile_table_load.argtypes = [ctypes.c_char_p]
+        L.pe_status_string.restype = ctypes.c_char_p
+        L.pe_status_string.argtypes = [ctypes.c_int]
+        L.pe_last_error.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        detail = lib().pe_last_error().decode() if st == 5 else ""
+        raise PEError(st, where, detail)
+
+
+# ------------------------------------------------------------------ offline
+@dataclass
+class Coeffs:
+    abc: np.ndarray       # (T, 3)
+    bounds: np.ndarray    # (T+1, 2): l_t, u_t
+    err_bound: float      # 1 - l_{T+1}
+    iters: np.ndarray     # (T,) Remez exchanges (0 = Newton-Schulz step)
+
+
+def coeffs(ell: float = 1e-3, T: int = 5, cushion: float | None = None, safety: float | None = None,
+           safety_on_last: bool = True) -> Coeffs:
+    """Greedy minimax schedule (pe_coeffs, host FP64)."""
+    L = lib()
+    o = CoeffOpts()
+    L.pe_coeff_opts_default(ctypes.byref(o))
+    if cushion is not None:
+        o.cushion = cushion
+    if safety is not None:
+        o.safety = safety
+    o.safety_on_last = 1 if safety_on_last else 0
+    abc = np.zeros(3 * T)
+    bounds = np.zeros(2 * (T + 1))
+    err = ctypes.c_double(0.0)
+    iters = np.zeros(T, dtype=np.int32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    st = L.pe_coeffs(float(ell), int(T), ctypes.byref(o), abc.ctypes.data_as(dp),
+                     bounds.ctypes.data_as(dp), ctypes.byref(err),
+                     iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    _check(st, "pe_coeffs")
+    return Coeffs(abc.reshape(T, 3), bounds.reshape(T + 1, 2), err.value, iters)
+
+
+# ------------------------------------------------------------------- online
+def _dtype_code(dt):
+    import torch
+    if dt == torch.float32:
+        return PE_F32
+    if dt == torch.bfloat16:
+        return PE_BF16
+    raise TypeError(f"unsupported dtype {dt} (float32 or bfloat16)")
+
+
+def _matrix(G, X) -> Matrix:
+    if G.dim() != 2 or X.dim() != 2 or tuple(G.shape) != tuple(X.shape):
+        raise ValueError("G and X must be 2-D of equal shape")
+    if not G.is_cuda or not X.is_cuda:
+        raise ValueError("G and X must be device tensors")
+    m, n = G.shape
+    if m > 0 and n > 0 and (G.stride(1) != 1 or X.stride(1) != 1):
+        raise ValueError("rows of G and X must be contiguous")
+    return Matrix(G.data_ptr(), X.data_ptr(), m, n, max(G.stride(0), n), max(X.stride(0), n),
+                  _dtype_code(G.dtype), _dtype_code(X.dtype))
+
+
+def _opts(T, abc, compute, fp8_steps, norm_mode, tile):
+    abc = np.ascontiguousarray(np.asarray(abc, dtype=np.float64).reshape(-1))
+    if abc.size != 3 * T:
+        raise ValueError("abc must hold 3*T coefficients")
+    o = Opts(int(T), abc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), COMPUTE[compute],
+             int(fp8_steps), int(norm_mode), int(tile))
+    return o, abc
+
+
+def _schedule(T, ell, abc):
+    if abc is None:
+        abc = coeffs(ell, T).abc
+    return np.asarray(abc, dtype=np.float64).reshape(T, 3)
+
+
+def _workspace(nbytes, device):
+    import torch
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    base = buf.data_ptr()
+    off = (-base) % 256
+    return buf, base + off
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def workspace_size(shapes, T=5, compute="bf16", fp8_steps=0) -> int:
+    mats = (Matrix * max(1, len(shapes)))()
+    for i, (m, n) in enumerate(shapes):
+        mats[i] = Matrix(1, 1, m, n, n, n, PE_BF16, PE_BF16)
+    o, _keep = _opts(T, np.zeros(3 * T), compute, fp8_steps, 0, 0)
+    return int(lib().pe_workspace_size(len(shapes), mats, ctypes.byref(o)))
+
+
+def polar(G, T: int = 5, ell: float = 1e-3, abc=None, compute: str = "bf16", out=None,
+          out_dtype=None, fp8_steps: int = 0, norm_mode: int = 0, tile: int = 0, stream=None):
+    """X_T for one matrix (pe_polar).  Returns a new tensor unless ``out`` is given."""
+    return polar_batched([G], T, ell, abc, compute, [out] if out is not None else None,
+                         out_dtype, fp8_steps, norm_mode, tile, stream, _single=True)[0]
+
+
+def polar_batched(Gs, T: int = 5, ell: float = 1e-3, abc=None, compute: str = "bf16", outs=None,
+                  out_dtype=None, fp8_steps: int = 0, norm_mode: int = 0, tile: int = 0,
+                  stream=None, _single: bool = False):
+    """X_T for a list of matrices of any shapes (pe_polar_batched)."""
+    import torch
+    Gs = list(Gs)
+    if outs is None:
+        outs = [torch.empty(G.shape, dtype=out_dtype or G.dtype, device=G.device) for G in Gs]
+    sched = _schedule(T, ell, abc)
+    o, _keep = _opts(T, sched, compute, fp8_steps, norm_mode, tile)
+    mats = (Matrix * max(1, len(Gs)))()
+    for i, (G, X) in enumerate(zip(Gs, outs)):
+        mats[i] = _matrix(G, X)
+    L = lib()
+    nbytes = int(L.pe_workspace_size(len(Gs), mats, ctypes.byref(o)))
+    if nbytes == 0 and len(Gs) > 0:
+        _check(1, "pe_workspace_size")
+    dev = Gs[0].device if Gs else None
+    ws_buf, ws = _workspace(nbytes, dev) if Gs else (None, 0)
+    st = _stream(stream)
+    if _single:
+        rc = L.pe_polar(mats, ctypes.byref(o), ctypes.c_void_p(ws), nbytes, st)
+        where = "pe_polar"
+    else:
+        rc = L.pe_polar_batched(len(Gs), mats, ctypes.byref(o), ctypes.c_void_p(ws), nbytes, st)
+        where = "pe_polar_batched"
+    _check(rc, where)
+    if ws_buf is not None:
+        # keep the workspace alive until the stream has consumed it
+        ws_buf.record_stream(torch.cuda.current_stream() if stream is None else stream)
+    return outs
+
+
+class Plan:
+    """Tile tables built once and the T-step sequence captured as a hipGraph."""
+
+    def __init__(self, Gs, outs=None, T: int = 5, ell: float = 1e-3, abc=None, compute: str = "bf16",
+                 out_dtype=None, fp8_steps: int = 0, norm_mode: int = 0, tile: int = 0, stream=None):
+        import torch
+        self.Gs = list(Gs)
+        self.outs = outs if outs is not None else [
+            torch.empty(G.shape, dtype=out_dtype or G.dtype, device=G.device) for G in self.Gs]
+        self.T = T
+        self.abc = _schedule(T, ell, abc)
+        o, self._abc_keep = _opts(T, self.abc, compute, fp8_steps, norm_mode, tile)
+        self._mats = (Matrix * max(1, len(self.Gs)))()
+        for i, (G, X) in enumerate(zip(self.Gs, self.outs)):
+            self._mats[i] = _matrix(G, X)
+        L = lib()
+        self.ws_bytes = int(L.pe_workspace_size(len(self.Gs), self._mats, ctypes.byref(o)))
+        if self.ws_bytes == 0:
+            _check(1, "pe_workspace_size")
+        self._ws_buf, self._ws = _workspace(self.ws_bytes, self.Gs[0].device)
+        h = ctypes.c_void_p()
+        _check(L.pe_plan_create(len(self.Gs), self._mats, ctypes.byref(o), ctypes.c_void_p(self._ws),
+                                self.ws_bytes, _stream(stream), ctypes.byref(h)), "pe_plan_create")
+        self._h = h
+
+    def launch(self, graph: bool = True, stream=None):
+        _check(lib().pe_plan_launch(self._h, _stream(stream), 1 if graph else 0), "pe_plan_launch")
+        return self.outs
+
+    def launch_phase(self, step: int, phase: int, stream=None):
+        """Diagnostic: one phase (0 norm, 1 Gram, 2 A^2+combine, 3 update) of one step."""
+        _check(lib().pe_plan_launch_phase(self._h, int(step), int(phase), _stream(stream)),
+               "pe_plan_launch_phase")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pe_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,89 @@
+// Device-side descriptors shared by the kernels and the host runtime.
+//
+// Layout in HBM (per matrix; all buffers 256-byte aligned, inside the caller's
+// workspace).  The iterate is oriented as X = G (m <= n) or X = G^T (m > n),
+// so X is s x L with s = min(m, n) <= L = max(m, n) and the Gram matrix is
+// s x s (the smaller side).  s and L are padded with zeros to sp, Lp
+// (multiples of 128).  Zero rows/columns stay exactly zero under
+// X <- aX + (bA + cA^2)X, so every kernel runs on the padded shape with no
+// bounds checks; only the input read and the final store see m, n.
+//   Xf      sp x Lp  fp32   master iterate (row-major)
+//   Xb      sp x Lp  bf16   operand copy of X for the Gram product (bf16/fp8 paths)
+//   XT[2]   Lp x sp  bf16 or fp32   X^T operand for B X (ping-pong across steps)
+//   Af      sp x sp  fp32   A = X X^T
+//   As      sp x sp  bf16   operand copy of A (fp32 path: Af itself)
+//   Bs      sp x sp  bf16 or fp32   B = bA + cA^2
+//   part    split-K partial tiles of the Gram-side products
+//   red     per-tile partial sums of squares (fp64) and maxima (fp32) of G
+//   scal    per-matrix scalars (scale, amax values), cnt: arrival counters
+#pragma once
+#include <stdint.h>
+
+namespace pe {
+
+constexpr int kTile = 128;      // GEMM block tile (M = N = 128)
+constexpr int kPad = 128;       // padding of s and L
+constexpr int kPrepTile = 64;   // norm/prep tile
+constexpr int kThreads = 256;   // threads per block (4 wave64)
+constexpr int kMaxSteps = 64;
+
+enum Prec : int32_t { kF32 = 0, kBF16 = 1, kFP8 = 2 };
+
+// scal[] slots
+enum : int32_t {
+  kScScale = 0,    // sigma = 1 / (1.01 ||G||_F + 1e-7)
+  kScAmaxG = 1,    // max |G| (float bits)
+  kScFro = 2,      // ||G||_F as float
+  kScAmaxX = 8,    // +t : max |X_t| (uint bits of a non-negative float), t = 0..63
+  kScAmaxA = 72,   // +t : max |A_t| for step t (0-based)
+  kScN = 136
+};
+
+struct MatDesc {
+  const void* G;
+  void* Out;
+  int64_t ldg, ldo;
+  int32_t m, n, s, L;
+  int32_t sp, Lp, trans, g_bf16;
+  int32_t out_bf16, nb, nbL, sel;
+  float* Xf;
+  void* Xb;
+  void* XT0;
+  void* XT1;
+  float* Af;
+  void* As;
+  void* Bs;
+  float* part;
+  double* red;      // [n_prep] doubles then [n_prep] floats
+  float* scal;      // [kScN]
+  uint32_t* cnt;    // [4]
+  int32_t n_prep, syrk_nt, upd_nt, gram_split;
+  int32_t a2_split, pad0, pad1, pad2;
+};
+
+struct KArgs {
+  const MatDesc* descs;  // device array of `count` descriptors
+  const int32_t* offs;   // per-matrix prefix offsets of this phase's items, count+1
+  int32_t count;
+  int32_t total;         // items in this launch
+  int32_t t;             // 0-based step
+  int32_t last;          // 1 on the final step
+  int32_t fp8;           // this step's Gram-side products take e4m3 operands
+  int32_t fp8_next;      // the next step's Gram product takes e4m3 operands
+  int32_t norm_mode;
+  int32_t tmax;          // rows of the selectable coefficient table
+  float a, b, c;         // coefficients of step t (fixed schedule)
+  const float* sel_coef; // [n_sched][tmax][3] or nullptr
+};
+
+// Device memory is filled from kernel arguments (copied at launch), so the
+// host needs neither pinned staging nor a synchronisation to upload tables.
+constexpr int kPutWords = 960;
+struct PutChunk {
+  uint32_t* dst;
+  int32_t nwords;
+  int32_t pad;
+  uint32_t w[kPutWords];
+};
+
+}  // namespace pe

@@ -1,0 +1,438 @@
+// Host runtime of the C ABI in pe.h: argument checks, workspace layout, tile
+// tables, launch sequence of the online stage, plans and hipGraph capture.
+//
+// Launch sequence for T steps (Section 3.5 / the Appendix A.1 listing, with
+// the scale folded into step 1):
+//   prep                                   ||G||_F, max|G|, X_0 copies
+//   for t: gram [+ reduce], a2 [+ reduce], update
+// Each launch covers every matrix of the call (grouped, persistent blocks).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pe.h"
+#include "pe_device.h"
+
+namespace pe {
+hipError_t launch_put(const PutChunk& c, hipStream_t st);
+hipError_t launch_init(const MatDesc* descs, int count, hipStream_t st);
+hipError_t launch_prep(int prec, const KArgs& a, int grid_cap, hipStream_t st);
+hipError_t launch_gemm(int prec, int kind, const KArgs& a, int grid_cap, hipStream_t st);
+hipError_t launch_reduce(int prec, int kind, const KArgs& a, int grid_cap, hipStream_t st);
+}  // namespace pe
+
+using namespace pe;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+enum Phase { PH_PREP = 0, PH_GRAM, PH_A2, PH_UPD, PH_RGRAM, PH_RA2, PH_N };
+
+constexpr int kGemmGridCap = 512;    // 2 resident blocks per CU x 256 CUs
+constexpr int kPrepGridCap = 2048;
+constexpr int kReduceGridCap = 1024;
+constexpr int kFillTarget = 512;     // Gram-side items wanted per launch
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+pe_status hip_fail(hipError_t e, const char* where) {
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+  g_last_error = buf;
+  return PE_EHIP;
+}
+
+struct Layout {
+  std::vector<MatDesc> descs;           // device pointers filled when ws != nullptr
+  std::vector<int32_t> offs[PH_N];      // count + 1 each
+  int32_t totals[PH_N] = {0};
+  size_t bytes = 0;
+  size_t descs_off = 0, offs_off = 0;
+};
+
+bool valid_matrix(const pe_matrix& m) {
+  if (m.m < 0 || m.n < 0) return false;
+  if (m.m == 0 || m.n == 0) return true;
+  if (!m.G || !m.X) return false;
+  if (m.ldg < m.n || m.ldx < m.n) return false;
+  if (m.g_dtype != PE_F32 && m.g_dtype != PE_BF16) return false;
+  if (m.x_dtype != PE_F32 && m.x_dtype != PE_BF16) return false;
+  if (m.m > (1 << 20) || m.n > (1 << 20)) return false;
+  return true;
+}
+
+pe_status check_opts(const pe_opts* o) {
+  if (!o) return PE_EINVAL;
+  if (o->T < 1 || o->T > kMaxSteps || !o->abc) return PE_EINVAL;
+  if (o->compute < PE_COMPUTE_F32 || o->compute > PE_COMPUTE_FP8) return PE_EINVAL;
+  if (o->norm_mode != 0 && o->norm_mode != 1) return PE_EINVAL;
+  if (o->compute == PE_COMPUTE_FP8) {
+    if (o->fp8_steps < 0 || o->fp8_steps > o->T - 1) return PE_EINVAL;
+    if (o->fp8_steps > 0) return PE_EUNSUPPORTED;
+  }
+  for (int i = 0; i < 3 * o->T; ++i)
+    if (!std::isfinite(o->abc[i])) return PE_EINVAL;
+  return PE_OK;
+}
+
+int prec_of(const pe_opts* o) { return o->compute == PE_COMPUTE_F32 ? kF32 : kBF16; }
+
+// Build the per-matrix descriptors and the item tables.  With ws == nullptr
+// only sizes are computed.
+pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char* ws, Layout* L) {
+  const int prec = prec_of(o);
+  const size_t esz = prec == kF32 ? 4 : 2;
+  L->descs.clear();
+  for (int p = 0; p < PH_N; ++p) L->offs[p].assign(1, 0);
+  // first pass: shapes and Gram-side tile counts (for the split-K choice)
+  struct Shape { int64_t s, L, sp, Lp; int nb, nbL, syrk, upd, prep; };
+  std::vector<Shape> sh;
+  int64_t syrk_total = 0;
+  for (int i = 0; i < count; ++i) {
+    const pe_matrix& m = mats[i];
+    Shape q{};
+    if (m.m > 0 && m.n > 0) {
+      q.s = std::min(m.m, m.n);
+      q.L = std::max(m.m, m.n);
+      q.sp = round_up(q.s, kPad);
+      q.Lp = round_up(q.L, kPad);
+      q.nb = (int)(q.sp / kTile);
+      q.nbL = (int)(q.Lp / kTile);
+      q.syrk = q.nb * (q.nb + 1) / 2;
+      q.upd = q.nb * q.nbL;
+      q.prep = (int)((q.sp / kPrepTile) * (q.Lp / kPrepTile));
+      syrk_total += q.syrk;
+    }
+    sh.push_back(q);
+  }
+  const int want = syrk_total > 0 ? (int)std::min<int64_t>(64, (kFillTarget + syrk_total - 1) / syrk_total) : 1;
+  size_t off = 0;
+  L->descs_off = off;
+  off = align_up(off + sizeof(MatDesc) * (size_t)std::max(count, 1));
+  L->offs_off = off;
+  off = align_up(off + sizeof(int32_t) * (size_t)PH_N * (count + 1));
+  for (int i = 0; i < count; ++i) {
+    const pe_matrix& m = mats[i];
+    const Shape& q = sh[i];
+    MatDesc d;
+    memset(&d, 0, sizeof d);
+    d.G = m.G;
+    d.Out = m.X;
+    d.ldg = m.ldg;
+    d.ldo = m.ldx;
+    d.m = (int32_t)m.m;
+    d.n = (int32_t)m.n;
+    d.s = (int32_t)q.s;
+    d.L = (int32_t)q.L;
+    d.sp = (int32_t)q.sp;
+    d.Lp = (int32_t)q.Lp;
+    d.trans = m.m > m.n;
+    d.g_bf16 = m.g_dtype == PE_BF16;
+    d.out_bf16 = m.x_dtype == PE_BF16;
+    d.nb = q.nb;
+    d.nbL = q.nbL;
+    d.n_prep = q.prep;
+    d.syrk_nt = q.syrk;
+    d.upd_nt = q.upd;
+    // split-K: enough Gram-side items to fill the GPU, at least 4 k-stages per split
+    const int bk = prec == kF32 ? 32 : 64;
+    const int max_gram = std::max<int64_t>(1, q.Lp / (4 * bk));
+    const int max_a2 = std::max<int64_t>(1, q.sp / (4 * bk));
+    d.gram_split = q.syrk ? std::min(want, max_gram) : 1;
+    d.a2_split = q.syrk ? std::min(want, max_a2) : 1;
+    if (q.syrk) {
+      auto take = [&](size_t bytes) {
+        char* p = ws ? ws + off : nullptr;
+        off = align_up(off + bytes);
+        return (void*)p;
+      };
+      const size_t X = (size_t)q.sp * q.Lp, A = (size_t)q.sp * q.sp;
+      d.Xf = (float*)take(X * 4);
+      d.Xb = prec == kF32 ? nullptr : take(X * 2);
+      d.XT0 = take(X * esz);
+      d.XT1 = take(X * esz);
+      d.Af = (float*)take(A * 4);
+      d.As = prec == kF32 ? (void*)d.Af : take(A * 2);
+      d.Bs = take(A * esz);
+      const int split = std::max(d.gram_split, d.a2_split);
+      d.part = split > 1 ? (float*)take((size_t)q.syrk * split * kTile * kTile * 4) : nullptr;
+      d.red = (double*)take((size_t)q.prep * 12 + 16);
+      d.scal = (float*)take(kScN * 4);
+      d.cnt = (uint32_t*)take(64);
+    }
+    L->descs.push_back(d);
+    auto push = [&](int ph, int n) { L->offs[ph].push_back(L->offs[ph].back() + n); };
+    push(PH_PREP, q.syrk ? q.prep : 0);
+    push(PH_GRAM, q.syrk ? q.syrk * d.gram_split : 0);
+    push(PH_A2, q.syrk ? q.syrk * d.a2_split : 0);
+    push(PH_UPD, q.syrk ? q.upd : 0);
+    push(PH_RGRAM, (q.syrk && d.gram_split > 1) ? q.syrk : 0);
+    push(PH_RA2, (q.syrk && d.a2_split > 1) ? q.syrk : 0);
+  }
+  for (int p = 0; p < PH_N; ++p) L->totals[p] = L->offs[p].back();
+  L->bytes = off;
+  return PE_OK;
+}
+
+pe_status validate(int count, const pe_matrix* mats, const pe_opts* o) {
+  if (count < 0 || (count > 0 && !mats)) return PE_EINVAL;
+  if (count > 100000) return PE_EINVAL;
+  pe_status st = check_opts(o);
+  if (st != PE_OK) return st;
+  for (int i = 0; i < count; ++i)
+    if (!valid_matrix(mats[i])) return PE_EINVAL;
+  return PE_OK;
+}
+
+// Copy host words to device memory through kernel arguments (stream-ordered).
+pe_status put_words(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  const uint32_t* w = (const uint32_t*)src;
+  size_t nw = (bytes + 3) / 4;
+  uint32_t* d = (uint32_t*)dst;
+  while (nw > 0) {
+    PutChunk c;
+    memset(&c, 0, sizeof c);
+    const int n = (int)std::min<size_t>(nw, kPutWords);
+    c.dst = d;
+    c.nwords = n;
+    memcpy(c.w, w, (size_t)n * 4);
+    hipError_t e = launch_put(c, st);
+    if (e != hipSuccess) return hip_fail(e, "upload");
+    d += n;
+    w += n;
+    nw -= n;
+  }
+  return PE_OK;
+}
+
+}  // namespace
+
+struct pe_plan {
+  int count = 0;
+  int prec = kBF16;
+  int T = 0;
+  int norm_mode = 0;
+  std::vector<float> abc;
+  Layout L;
+  MatDesc* d_descs = nullptr;
+  int32_t* d_offs = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+pe_status upload(pe_plan* p, char* ws, hipStream_t st) {
+  p->d_descs = (MatDesc*)(ws + p->L.descs_off);
+  p->d_offs = (int32_t*)(ws + p->L.offs_off);
+  pe_status s = put_words(p->d_descs, p->L.descs.data(), sizeof(MatDesc) * p->L.descs.size(), st);
+  if (s != PE_OK) return s;
+  std::vector<int32_t> offs;
+  for (int ph = 0; ph < PH_N; ++ph) offs.insert(offs.end(), p->L.offs[ph].begin(), p->L.offs[ph].end());
+  return put_words(p->d_offs, offs.data(), offs.size() * 4, st);
+}
+
+KArgs base_args(const pe_plan* p) {
+  KArgs a;
+  memset(&a, 0, sizeof a);
+  a.descs = p->d_descs;
+  a.count = p->count;
+  a.norm_mode = p->norm_mode;
+  a.tmax = p->T;
+  return a;
+}
+
+void set_phase(const pe_plan* p, KArgs* a, int ph) {
+  a->offs = p->d_offs + (size_t)ph * (p->count + 1);
+  a->total = p->L.totals[ph];
+}
+
+void set_step(const pe_plan* p, KArgs* a, int t) {
+  a->t = t;
+  a->last = t == p->T - 1;
+  a->a = p->abc[3 * t + 0];
+  a->b = p->abc[3 * t + 1];
+  a->c = p->abc[3 * t + 2];
+}
+
+pe_status enqueue_norm(const pe_plan* p, hipStream_t st) {
+  KArgs a = base_args(p);
+  hipError_t e = launch_init(p->d_descs, p->count, st);
+  if (e != hipSuccess) return hip_fail(e, "init launch");
+  set_phase(p, &a, PH_PREP);
+  if ((e = launch_prep(p->prec, a, kPrepGridCap, st)) != hipSuccess) return hip_fail(e, "prep launch");
+  return PE_OK;
+}
+
+// kind: 0 Gram, 1 A^2 + combine, 2 update
+pe_status enqueue_gemm(const pe_plan* p, int t, int kind, hipStream_t st) {
+  static const int ph_main[3] = {PH_GRAM, PH_A2, PH_UPD};
+  static const int ph_red[3] = {PH_RGRAM, PH_RA2, -1};
+  static const char* names[3] = {"gram launch", "a2 launch", "update launch"};
+  KArgs a = base_args(p);
+  set_step(p, &a, t);
+  set_phase(p, &a, ph_main[kind]);
+  hipError_t e = launch_gemm(p->prec, kind, a, kGemmGridCap, st);
+  if (e != hipSuccess) return hip_fail(e, names[kind]);
+  if (ph_red[kind] >= 0 && p->L.totals[ph_red[kind]]) {
+    set_phase(p, &a, ph_red[kind]);
+    if ((e = launch_reduce(p->prec, kind, a, kReduceGridCap, st)) != hipSuccess)
+      return hip_fail(e, "split-k reduce");
+  }
+  return PE_OK;
+}
+
+pe_status enqueue(const pe_plan* p, hipStream_t st) {
+  if (p->L.totals[PH_PREP] == 0) return PE_OK;
+  pe_status s = enqueue_norm(p, st);
+  if (s != PE_OK) return s;
+  for (int t = 0; t < p->T; ++t)
+    for (int kind = 0; kind < 3; ++kind)
+      if ((s = enqueue_gemm(p, t, kind, st)) != PE_OK) return s;
+  return PE_OK;
+}
+
+pe_status plan_init(pe_plan* p, int count, const pe_matrix* mats, const pe_opts* o, void* ws,
+                    size_t ws_bytes, hipStream_t st) {
+  pe_status s = validate(count, mats, o);
+  if (s != PE_OK) return s;
+  p->count = count;
+  p->prec = prec_of(o);
+  p->T = o->T;
+  p->norm_mode = o->norm_mode;
+  p->abc.resize(3 * o->T);
+  for (int i = 0; i < 3 * o->T; ++i) p->abc[i] = (float)o->abc[i];
+  Layout sizing;
+  build_layout(count, mats, o, nullptr, &sizing);
+  if (sizing.totals[PH_PREP] == 0) return PE_OK;  // nothing but empty matrices
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < sizing.bytes) return PE_EWORKSPACE;
+  build_layout(count, mats, o, (char*)ws, &p->L);
+  return upload(p, (char*)ws, st);
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- C ABI
+extern "C" {
+
+size_t pe_workspace_size(int32_t count, const pe_matrix* mats, const pe_opts* opts) {
+  if (validate(count, mats, opts) != PE_OK) return 0;
+  Layout L;
+  build_layout(count, mats, opts, nullptr, &L);
+  return L.bytes;
+}
+
+pe_status pe_polar_batched(int32_t count, const pe_matrix* mats, const pe_opts* opts, void* ws,
+                           size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  hipStream_t st = (hipStream_t)stream;
+  pe_plan p;
+  pe_status s = plan_init(&p, count, mats, opts, ws, ws_bytes, st);
+  if (s != PE_OK) return s;
+  return enqueue(&p, st);
+}
+
+pe_status pe_polar(const pe_matrix* mat, const pe_opts* opts, void* ws, size_t ws_bytes, void* stream) {
+  if (!mat) return PE_EINVAL;
+  return pe_polar_batched(1, mat, opts, ws, ws_bytes, stream);
+}
+
+pe_status pe_plan_create(int32_t count, const pe_matrix* mats, const pe_opts* opts, void* ws,
+                         size_t ws_bytes, void* stream, pe_plan** plan) {
+  g_last_error.clear();
+  if (!plan) return PE_EINVAL;
+  *plan = nullptr;
+  pe_plan* p = new pe_plan();
+  pe_status s = plan_init(p, count, mats, opts, ws, ws_bytes, (hipStream_t)stream);
+  if (s != PE_OK) {
+    delete p;
+    return s;
+  }
+  *plan = p;
+  return PE_OK;
+}
+
+pe_status pe_plan_launch(pe_plan* p, void* stream, int32_t use_graph) {
+  g_last_error.clear();
+  if (!p) return PE_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (!use_graph) return enqueue(p, st);
+  hipError_t e;
+  if (!p->exec) {
+    // capture on a private stream (the caller's may be the legacy default stream)
+    if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(e, "capture stream");
+    // order the capture after the caller's pending work (tables were uploaded there)
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "sync before capture");
+    if ((e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_fail(e, "begin capture");
+    pe_status s = enqueue(p, p->cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->cap_stream, &g);
+    if (s != PE_OK) {
+      if (g) hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    p->graph = g;
+    if ((e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+      p->exec = nullptr;
+      return hip_fail(e, "graph instantiate");
+    }
+  }
+  if ((e = hipGraphLaunch(p->exec, st)) != hipSuccess) return hip_fail(e, "graph launch");
+  return PE_OK;
+}
+
+pe_status pe_plan_launch_phase(pe_plan* p, int32_t step, int32_t phase, void* stream) {
+  g_last_error.clear();
+  if (!p || step < 0 || step >= p->T || phase < 0 || phase > 3) return PE_EINVAL;
+  if (p->L.totals[PH_PREP] == 0) return PE_OK;
+  hipStream_t st = (hipStream_t)stream;
+  if (phase == 0) return enqueue_norm(p, st);
+  return enqueue_gemm(p, step, phase - 1, st);
+}
+
+pe_status pe_plan_destroy(pe_plan* p) {
+  if (!p) return PE_OK;
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+  delete p;
+  return PE_OK;
+}
+
+int32_t pe_tile_count(void) { return 1; }
+
+const char* pe_tile_name(int32_t tile_id) {
+  return tile_id == 0 ? "mfma16_bm128_bn128_w2x2" : nullptr;
+}
+
+pe_status pe_tile_table_load(const char* path) {
+  if (!path) return PE_EINVAL;
+  return PE_EUNSUPPORTED;
+}
+
+const char* pe_status_string(pe_status st) {
+  switch (st) {
+    case PE_OK: return "ok";
+    case PE_EINVAL: return "invalid argument";
+    case PE_EUNSUPPORTED: return "unsupported in this build";
+    case PE_ENOCONV: return "Remez exchange did not converge";
+    case PE_EWORKSPACE: return "workspace missing, too small or not 256-byte aligned";
+    case PE_EHIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char* pe_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+"""Host-side checks of the C ABI (no GPU): the library loads and exports every
+entry point declared in include/pe.h, the host FP64 schedule matches the oracle
+and the paper's table, and argument checks reject bad input before any launch."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2505_16932_amd as pe
+from oracle import schedule as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "pe.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pe_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = pe.lib()
+    syms = _declared_symbols()
+    assert "pe_polar" in syms and "pe_coeffs" in syms and "pe_polar_batched" in syms
+    for name in syms:
+        assert hasattr(L, name), name
+
+
+def test_coeffs_match_oracle_and_paper(golden_dir):
+    paper = np.loadtxt(os.path.join(golden_dir, "paper_coeffs_ell1e-3.txt"))
+    c = pe.coeffs(1e-3, 8, safety=1.0)
+    rel = np.abs(c.abc - paper) / np.abs(paper)
+    assert rel[:6].max() <= 1e-13
+    assert rel[6].max() <= 2e-10
+    assert np.array_equal(c.abc[7], paper[7])
+    o = S.greedy_schedule(1e-3, 8, safety=1.0)
+    assert np.allclose(c.bounds[:, 0], o.ell, rtol=1e-12, atol=1e-15)
+    assert np.allclose(c.bounds[:, 1], o.u, rtol=1e-12)
+    assert abs(c.err_bound - o.err_bound) <= 1e-12
+    assert list(c.iters) == list(o.remez_iters)
+
+
+@pytest.mark.parametrize("ell,T", [(1e-3, 5), (1e-3, 6), (1e-2, 7), (1e-4, 10), (0.3, 3)])
+def test_coeffs_safety_variants(ell, T):
+    for kw in [dict(), dict(safety_on_last=False), dict(cushion=0.0), dict(cushion=-1.0)]:
+        c = pe.coeffs(ell, T, **kw)
+        o = S.greedy_schedule(ell, T, cushion=0.0 if kw.get("cushion") == 0.0 else S.CUSHION,
+                              safety_on_last=kw.get("safety_on_last", True),
+                              tenth_rule=kw.get("cushion") == -1.0)
+        # two float64 exchanges agree to within the conditioning of each step's
+        # 4x4 system, which grows without bound as l_t/u_t -> 1 (Appendix E)
+        for t in range(T):
+            if kw.get("cushion") == -1.0:
+                lo = max(o.ell[t], o.u[t] / 10)
+            else:
+                lo = max(o.ell[t], (0.0 if kw.get("cushion") == 0.0 else S.CUSHION) * o.u[t])
+            hi = o.u[t]
+            pts = np.array([lo, 0.75 * lo + 0.25 * hi, 0.25 * lo + 0.75 * hi, hi])
+            cond = np.linalg.cond(np.stack([pts, pts ** 3, pts ** 5, [1, -1, 1, -1]], 1))
+            tol = max(1e-13, 100 * cond * np.finfo(float).eps) if np.isfinite(cond) else 1.0
+            assert np.allclose(c.abc[t], o.abc[t], rtol=tol, atol=1e-14), (kw, t, tol)
+
+
+def test_coeffs_invalid_arguments():
+    L = pe.lib()
+    abc = (ctypes.c_double * 30)()
+    for ell, T in [(0.0, 5), (1.0, 5), (-1.0, 5), (1e-3, 0), (1e-3, 65), (float("nan"), 3)]:
+        assert L.pe_coeffs(ell, T, None, abc, None, None, None) == 1
+    assert L.pe_coeffs(1e-3, 5, None, None, None, None, None) == 1
+
+
+def _opts(T=5, compute=1, fp8=0):
+    abc = np.tile(np.array(S.NS5), (T, 1)).reshape(-1).copy()
+    o = pe.Opts(T, abc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), compute, fp8, 0, 0)
+    return o, abc
+
+
+def test_workspace_and_argument_checks():
+    L = pe.lib()
+    o, keep = _opts()
+    m = pe.Matrix(16, 32, 300, 200, 200, 200, 1, 1)
+    n1 = L.pe_workspace_size(1, ctypes.byref(m), ctypes.byref(o))
+    assert n1 > 0
+    # padded to 256 x 384 bf16 path: X fp32 + bf16 + 2 XT bf16 + A fp32/bf16 + B bf16
+    assert n1 >= 256 * 384 * (4 + 2 + 2 + 2) + 256 * 256 * (4 + 2 + 2)
+    bad = [pe.Matrix(16, 32, 300, 200, 100, 200, 1, 1),   # ldg < n
+           pe.Matrix(0, 32, 300, 200, 200, 200, 1, 1),    # null G
+           pe.Matrix(16, 32, -1, 200, 200, 200, 1, 1),    # negative m
+           pe.Matrix(16, 32, 3, 2, 2, 2, 7, 1)]           # bad dtype
+    for b in bad:
+        assert L.pe_workspace_size(1, ctypes.byref(b), ctypes.byref(o)) == 0
+        assert L.pe_polar(ctypes.byref(b), ctypes.byref(o), None, 0, None) == 1
+    o2, keep2 = _opts(T=0)
+    assert L.pe_polar(ctypes.byref(m), ctypes.byref(o2), None, 0, None) == 1
+    # workspace too small or misaligned: rejected before any launch
+    assert L.pe_polar(ctypes.byref(m), ctypes.byref(o), None, 0, None) == 4
+    assert L.pe_polar(ctypes.byref(m), ctypes.byref(o), ctypes.c_void_p(256), 16, None) == 4
+    assert L.pe_polar(ctypes.byref(m), ctypes.byref(o), ctypes.c_void_p(257), n1, None) == 4
+    # m = 0 is a valid no-op that needs no workspace and launches nothing
+    z = pe.Matrix(0, 0, 0, 7, 7, 7, 1, 1)
+    assert L.pe_polar(ctypes.byref(z), ctypes.byref(o), None, 0, None) == 0
+    assert L.pe_polar_batched(0, None, ctypes.byref(o), None, 0, None) == 0
+    assert L.pe_status_string(4) == b"workspace missing, too small or not 256-byte aligned"

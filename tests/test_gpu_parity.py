@@ -1,0 +1,185 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: relative Frobenius error to the FP64 same iteration on the same input
+values <= 1e-5 for the FP32 path and <= 3e-2 for the bf16 path (FP32 master,
+bf16 MFMA operands); the polar error ||X_T - U V^T||_2 is reported where U V^T
+is known by construction.  Shapes span several 128-wide tiles, ragged tails,
+both orientations, split-K and grouped (batched) launches.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import (device_input, oracle_same_iteration, oracle_schedule, polar_error,
+                            relf, to_np)
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "bf16": 3e-2}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def pe():
+    import paper_2505_16932_amd as pe
+    pe.lib()
+    return pe
+
+
+def _check(pe, torch, G64, T, compute, dtype, tol=None, **kw):
+    G, vals = device_input(G64, dtype)
+    abc = oracle_schedule(T)
+    X = pe.polar(G, T=T, abc=abc, compute=compute, out_dtype=torch.float32, **kw)
+    torch.cuda.synchronize()
+    ref = oracle_same_iteration(vals, abc)
+    err = relf(to_np(X), ref)
+    bar = tol if tol is not None else TOL[compute]
+    print(f"[parity] shape={G64.shape} compute={compute} T={T} relF={err:.3e} bar={bar}", flush=True)
+    assert np.isfinite(err) and err <= bar, err
+    return to_np(X), ref
+
+
+def test_config1_fp32_gaussian_256(pe, torch_cuda):
+    """256 x 256 iid N(0,1), seed 1001, FP32, T = 5, l = 1e-3."""
+    S = synth.gaussian(1001)
+    X, ref = _check(pe, torch_cuda, S.G, 5, "f32", torch_cuda.float32)
+    from oracle.jacobi import polar_jacobi
+    perr = polar_error(X, polar_jacobi(S.G))
+    print(f"[polar-error] config1 ||X-UV^T||_2 = {perr:.4f}", flush=True)
+
+
+@pytest.mark.parametrize("shape", [(200, 333), (333, 200), (130, 1000), (1, 50), (50, 1),
+                                   (257, 257), (7, 3), (384, 384)])
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_ragged_shapes(pe, torch_cuda, shape, compute):
+    r = synth.rng(500 + shape[0] * 3 + shape[1])
+    G64 = r.standard_normal(shape)
+    dtype = torch_cuda.float32 if compute == "f32" else torch_cuda.bfloat16
+    _check(pe, torch_cuda, G64, 5, compute, dtype)
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_split_k_wide_gram(pe, torch_cuda, compute):
+    """s = 128, L = 8192: one Gram tile, so the Gram and A^2 products split K."""
+    r = synth.rng(601)
+    G64 = synth.usv(r, 128, 8192, synth.spectrum_loguniform(r, 128, 1e-3, 1.0)).G
+    dtype = torch_cuda.float32 if compute == "f32" else torch_cuda.bfloat16
+    _check(pe, torch_cuda, G64, 6, compute, dtype)
+
+
+def test_fp32_input_bf16_output(pe, torch_cuda):
+    r = synth.rng(602)
+    G64 = r.standard_normal((300, 520))
+    G, vals = device_input(G64, torch_cuda.float32)
+    abc = oracle_schedule(5)
+    X = pe.polar(G, T=5, abc=abc, compute="bf16", out_dtype=torch_cuda.bfloat16)
+    ref = oracle_same_iteration(vals, abc)
+    assert X.dtype == torch_cuda.bfloat16
+    assert relf(to_np(X), ref) <= 3e-2
+
+
+def test_orientation_is_exact_transpose(pe, torch_cuda):
+    """polar(G^T) = polar(G)^T: the tall input runs on the same oriented X."""
+    r = synth.rng(603)
+    G = torch_cuda.from_numpy(r.standard_normal((190, 450)).astype(np.float32)).cuda()
+    X1 = pe.polar(G, T=5, compute="bf16")
+    X2 = pe.polar(G.t().contiguous(), T=5, compute="bf16")
+    torch_cuda.cuda.synchronize()
+    assert torch_cuda.equal(X1, X2.t())
+
+
+def test_deterministic(pe, torch_cuda):
+    r = synth.rng(604)
+    G = torch_cuda.from_numpy(r.standard_normal((640, 2000)).astype(np.float32)).cuda().bfloat16()
+    X1 = pe.polar(G, T=5, compute="bf16")
+    X2 = pe.polar(G, T=5, compute="bf16")
+    torch_cuda.cuda.synchronize()
+    assert torch_cuda.equal(X1, X2)
+
+
+def test_zero_and_empty(pe, torch_cuda):
+    G = torch_cuda.zeros((100, 300), device="cuda")
+    X = pe.polar(G, T=5, compute="f32")
+    torch_cuda.cuda.synchronize()
+    assert torch_cuda.count_nonzero(X).item() == 0
+    E = torch_cuda.zeros((0, 5), device="cuda")
+    assert pe.polar(E, T=5).shape == (0, 5)
+
+
+def test_strided_input_and_output(pe, torch_cuda):
+    """Row-major views with leading dimension > n (ld = stride(0))."""
+    r = synth.rng(605)
+    big = torch_cuda.from_numpy(r.standard_normal((260, 700)).astype(np.float32)).cuda()
+    G = big[:, 50:450]
+    out_big = torch_cuda.full((260, 900), 7.0, device="cuda")
+    out = out_big[:, 100:500]
+    abc = oracle_schedule(5)
+    pe.polar(G, T=5, abc=abc, compute="f32", out=out)
+    torch_cuda.cuda.synchronize()
+    ref = oracle_same_iteration(G.cpu().double().numpy(), abc)
+    assert relf(to_np(out), ref) <= 1e-5
+    assert torch_cuda.all(out_big[:, :100] == 7.0) and torch_cuda.all(out_big[:, 500:] == 7.0)
+
+
+def test_batched_uneven(pe, torch_cuda):
+    """Grouped launches over matrices of uneven shapes and both orientations."""
+    shapes = [(256, 768), (768, 256), (130, 130), (64, 1000), (1000, 64), (384, 1152), (5, 9)]
+    Gs, vals = [], []
+    for k, s in enumerate(shapes):
+        g, v = device_input(synth.rng(700 + k).standard_normal(s), torch_cuda.bfloat16)
+        Gs.append(g)
+        vals.append(v)
+    abc = oracle_schedule(5)
+    Xs = pe.polar_batched(Gs, T=5, abc=abc, compute="bf16", out_dtype=torch_cuda.float32)
+    torch_cuda.cuda.synchronize()
+    for X, v, s in zip(Xs, vals, shapes):
+        err = relf(to_np(X), oracle_same_iteration(v, abc))
+        print(f"[batched] {s} relF={err:.3e}", flush=True)
+        assert err <= 3e-2
+    # the grouped path computes each matrix exactly as the single path does
+    for G, X in zip(Gs[:3], Xs[:3]):
+        Y = pe.polar(G, T=5, abc=abc, compute="bf16", out_dtype=torch_cuda.float32)
+        torch_cuda.cuda.synchronize()
+        assert relf(to_np(Y), to_np(X)) <= 1e-6
+
+
+def test_plan_graph_replays(pe, torch_cuda):
+    """hipGraph replays match the eager launch bit for bit, with eager work and
+    synchronisations between replays."""
+    shapes = [(256, 512), (512, 256), (300, 300)]
+    Gs = [torch_cuda.from_numpy(synth.rng(800 + k).standard_normal(s).astype(np.float32)).cuda().bfloat16()
+          for k, s in enumerate(shapes)]
+    plan = pe.Plan(Gs, T=5, compute="bf16")
+    eager = [x.clone() for x in plan.launch(graph=False)]
+    torch_cuda.cuda.synchronize()
+    for rep in range(4):
+        junk = torch_cuda.randn(1000, device="cuda").sum()
+        plan.launch(graph=True)
+        torch_cuda.cuda.synchronize()
+        for a, b in zip(plan.outs, eager):
+            assert torch_cuda.equal(a, b), rep
+    plan.close()
+
+
+def test_loguniform_4096x1024_bf16(pe, torch_cuda):
+    """4096 x 1024 bf16, U diag(s) V^T with Haar U, V, s log-uniform in [1e-4, 1]
+    times a log-uniform factor in [0.1, 10]; T = 5..8; plain single-matrix path."""
+    S = synth.loguniform(1002)
+    G, vals = device_input(S.G, torch_cuda.bfloat16)
+    P = S.polar()
+    for T in (5, 8):
+        abc = oracle_schedule(T)
+        X = pe.polar(G, T=T, abc=abc, compute="bf16", out_dtype=torch_cuda.float32)
+        torch_cuda.cuda.synchronize()
+        ref = oracle_same_iteration(vals, abc)
+        Xn = to_np(X)
+        err = relf(Xn, ref)
+        print(f"[config2] T={T} relF={err:.3e} polar_err_gpu={polar_error(Xn, P):.4f} "
+              f"polar_err_fp64={polar_error(ref, P):.4f}", flush=True)
+        assert err <= 3e-2
