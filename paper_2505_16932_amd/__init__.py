@@ -69,6 +69,10 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2505_16932_amd.build` (no fallback path exists)")
+        # torch ships its own HIP runtime; import it first so that the library's
+        # libamdhip64.so.7 dependency resolves to that same loaded runtime
+        # (two HIP runtimes in one process do not share devices)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         L.pe_coeffs.restype = ctypes.c_int
         L.pe_coeffs.argtypes = [ctypes.c_double, ctypes.c_int32, ctypes.POINTER(CoeffOpts),
