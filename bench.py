@@ -124,6 +124,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--phase-reps", type=int, default=10)
+    ap.add_argument("--tile", type=int, default=0, help="0 auto, 1 = 128x128, 2 = 256x256 block tile")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -148,7 +149,7 @@ def main():
     abc = pe.coeffs(1e-3, T).abc
     stream = torch.cuda.current_stream()
 
-    plan = pe.Plan(Gs, T=T, abc=abc, compute=args.compute, fp8_steps=args.fp8_steps)
+    plan = pe.Plan(Gs, T=T, abc=abc, compute=args.compute, fp8_steps=args.fp8_steps, tile=args.tile)
     log(f"[bench] plan ready, workspace {plan.ws_bytes / 2**30:.1f} GiB")
     for _ in range(args.warmup):
         plan.launch(graph=True)
@@ -199,11 +200,13 @@ def main():
         # plain single-matrix path: one eager pe_polar per matrix, same schedule
         outs = [torch.empty_like(G) for G in Gs]
         for G, X in zip(Gs[:2], outs[:2]):
-            pe.polar(G, T=T, abc=abc, compute=args.compute, out=X, fp8_steps=args.fp8_steps)
+            pe.polar(G, T=T, abc=abc, compute=args.compute, out=X, fp8_steps=args.fp8_steps,
+                     tile=args.tile)
         torch.cuda.synchronize()
         e0.record(stream)
         for G, X in zip(Gs, outs):
-            pe.polar(G, T=T, abc=abc, compute=args.compute, out=X, fp8_steps=args.fp8_steps)
+            pe.polar(G, T=T, abc=abc, compute=args.compute, out=X, fp8_steps=args.fp8_steps,
+                     tile=args.tile)
         e1.record(stream)
         torch.cuda.synchronize()
         plain_ms = e0.elapsed_time(e1)
@@ -235,7 +238,7 @@ def main():
         "dtype": {"bf16": "bf16", "fp8": "fp8e4m3+bf16", "f32": "f32"}[args.compute],
         "data": "synthetic",
         "config": {"workload": args.workload, "matrices": len(Gs), "T": T, "ell": 1e-3,
-                   "compute": args.compute, "fp8_steps": args.fp8_steps,
+                   "compute": args.compute, "fp8_steps": args.fp8_steps, "tile": args.tile,
                    "shapes": sorted(set(shapes))},
         "pct_bf16_peak": round(100.0 * tflops / peak, 2),
         "matrices_per_s": round(len(Gs) / (ms * 1e-3), 2),

@@ -23,7 +23,10 @@ HIP_SOURCES = ["kernels.hip", "runtime.hip"]
 CXX_SOURCES = ["coeffs.cpp"]
 
 # Packed-FP32 instructions are kept out of every device build.
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                # the 256-tile epilogues (256 accumulators per lane) must unroll
+                # fully, or the accumulator array is indexed through scratch
+                "-mllvm", "-pragma-unroll-threshold=200000"]
 
 
 def _run(cmd):

@@ -36,7 +36,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-enum Kind : int { KIND_GRAM = 0, KIND_A2 = 1, KIND_UPD = 2 };
+enum Kind : int { KIND_GRAM = 0, KIND_A2 = 1, KIND_UPD = 2, KIND_UPD_LAST = 3 };
 
 // Descriptor pointers are generic; loads through these global-address-space
 // views compile to global_load (not flat_load), which keeps vmcnt/lgkmcnt apart.
@@ -224,10 +224,34 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(KArgs args) {
 }
 
 // ------------------------------------------------------------- GEMM core
-// LDS: per operand 128 rows x 144 bytes (128 B of k plus 16 B pad), two
-// operands, two buffers = 73728 bytes.
+// Block tile BT x BT (BT = 128 or 256), 4 wave64 in a 2 x 2 grid, each wave a
+// (BT/2) x (BT/2) tile of 4 x 4 MFMA fragments of F x F, F = BT/8:
+//   F = 16: v_mfma_f32_16x16x32_bf16 / v_mfma_f32_16x16x4_f32
+//   F = 32: v_mfma_f32_32x32x16_bf16 / v_mfma_f32_32x32x2_f32
+// One LDS stage holds 128 bytes of k per row (64 bf16 or 32 fp32) plus a
+// 16-byte pad (bank spread), for both operands; two stages are double-buffered.
+// A lane reads its fragment as one 16-byte chunk: rows lane % F, k-chunk
+// lane / F within a sub-step of F == 16 ? 64 : 32 bytes.
 constexpr int kRowBytes = 144;
-constexpr int kOpBytes = kTile * kRowBytes;
+
+template <int BT>
+struct TileCfg {
+  static constexpr int F = BT / 8;                   // fragment edge
+  static constexpr int OPB = BT * kRowBytes;         // bytes of one operand stage
+  static constexpr int LDS = 4 * OPB;                // 2 operands x 2 stages
+  static constexpr int SUBB = F == 16 ? 64 : 32;     // bytes of k per MFMA sub-step
+  static constexpr int NSUB = 128 / SUBB;            // sub-steps per stage
+  static constexpr int CPT = BT / 32;                // 16-byte chunks per thread per operand
+  static constexpr int ACC = F == 16 ? 4 : 16;       // accumulator floats per fragment
+  static constexpr int RG = F == 16 ? 1 : 4;         // groups of 4 consecutive rows per fragment
+};
+
+template <int N>
+struct AccT;
+template <>
+struct AccT<4> { typedef f32x4 type; };
+template <>
+struct AccT<16> { typedef float type __attribute__((ext_vector_type(16))); };
 
 template <typename T>
 struct OpT;
@@ -242,64 +266,75 @@ struct OpT<float> {
   static constexpr int kBK = 32;
 };
 
-template <typename T>
+template <typename T, int BT, typename A>
 __device__ __forceinline__ void mma_stage(const char* sA, const char* sB, int wm, int wn, int lane,
-                                          f32x4 (&acc)[4][4]) {
+                                          A (&acc)[4][4]) {
+  typedef TileCfg<BT> C;
+  constexpr int F = C::F;
 #pragma unroll
-  for (int ks = 0; ks < 2; ++ks) {
+  for (int ks = 0; ks < C::NSUB; ++ks) {
     u32x4 fa[4], fb[4];
-    const int koff = ks * 64 + (lane >> 4) * 16;
+    const int koff = ks * C::SUBB + (lane / F) * 16;
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      fa[f] = *(const u32x4*)(sA + (wm * 64 + f * 16 + (lane & 15)) * kRowBytes + koff);
-      fb[f] = *(const u32x4*)(sB + (wn * 64 + f * 16 + (lane & 15)) * kRowBytes + koff);
+      fa[f] = *(const u32x4*)(sA + (wm * (BT / 2) + f * F + (lane % F)) * kRowBytes + koff);
+      fb[f] = *(const u32x4*)(sB + (wn * (BT / 2) + f * F + (lane % F)) * kRowBytes + koff);
     }
 #pragma unroll
     for (int fm = 0; fm < 4; ++fm) {
 #pragma unroll
       for (int fn = 0; fn < 4; ++fn) {
         if constexpr (sizeof(T) == 2) {
-          acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              __builtin_bit_cast(bf16x8, fa[fm]), __builtin_bit_cast(bf16x8, fb[fn]), acc[fm][fn], 0,
-              0, 0);
+          if constexpr (F == 16)
+            acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                __builtin_bit_cast(bf16x8, fa[fm]), __builtin_bit_cast(bf16x8, fb[fn]), acc[fm][fn],
+                0, 0, 0);
+          else
+            acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, fa[fm]), __builtin_bit_cast(bf16x8, fb[fn]), acc[fm][fn],
+                0, 0, 0);
         } else {
           const f32x4 a4 = __builtin_bit_cast(f32x4, fa[fm]);
           const f32x4 b4 = __builtin_bit_cast(f32x4, fb[fn]);
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[e], b4[e], acc[fm][fn], 0, 0, 0);
+          for (int e = 0; e < 4; ++e) {
+            if constexpr (F == 16)
+              acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[e], b4[e], acc[fm][fn], 0, 0, 0);
+            else
+              acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[e], b4[e], acc[fm][fn], 0, 0, 0);
+          }
         }
       }
     }
   }
 }
 
-// acc += P[rp0:rp0+128, k0:k1] * Q[rq0:rq0+128, k0:k1]^T, (k1 - k0) % BK == 0.
-template <typename T>
+// acc += P[rp0:rp0+BT, k0:k1] * Q[rq0:rq0+BT, k0:k1]^T, (k1 - k0) % BK == 0.
+template <typename T, int BT, typename A>
 __device__ __forceinline__ void gemm_nt_tile(const T* __restrict__ P, const T* __restrict__ Q,
                                              int64_t ld, int rp0, int rq0, int k0, int k1,
-                                             char* smem, f32x4 (&acc)[4][4]) {
-  constexpr int BK = OpT<T>::kBK, VEC = OpT<T>::kVec;
+                                             char* smem, A (&acc)[4][4]) {
+  typedef TileCfg<BT> C;
+  constexpr int BK = OpT<T>::kBK, VEC = OpT<T>::kVec, CPT = C::CPT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  // thread's 4 chunks per operand: chunk c = tid + 256 j; row c/8, 16-byte column c%8
+  // chunk c = tid + 256 j: row c / 8, 16-byte column c % 8
   const int crow = tid >> 3, ccol = tid & 7;
   const PE_GLOBAL T* pP = gview(P) + (size_t)(rp0 + crow) * ld + k0 + ccol * VEC;
   const PE_GLOBAL T* pQ = gview(Q) + (size_t)(rq0 + crow) * ld + k0 + ccol * VEC;
   const size_t jstride = (size_t)32 * ld;  // 32 rows between a thread's chunks
-  u32x4 ra[4], rb[4];
+  u32x4 ra[CPT], rb[CPT];
   const int nk = (k1 - k0) / BK;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < CPT; ++j) {
     ra[j] = *(const PE_GLOBAL u32x4*)(pP + j * jstride);
     rb[j] = *(const PE_GLOBAL u32x4*)(pQ + j * jstride);
   }
-  char* sbase = smem;
   const int soff = crow * kRowBytes + ccol * 16;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    *(u32x4*)(sbase + soff + j * 32 * kRowBytes) = ra[j];
-    *(u32x4*)(sbase + kOpBytes + soff + j * 32 * kRowBytes) = rb[j];
+  for (int j = 0; j < CPT; ++j) {
+    *(u32x4*)(smem + soff + j * 32 * kRowBytes) = ra[j];
+    *(u32x4*)(smem + C::OPB + soff + j * 32 * kRowBytes) = rb[j];
   }
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
@@ -307,17 +342,17 @@ __device__ __forceinline__ void gemm_nt_tile(const T* __restrict__ P, const T* _
     // keeps the loop free of branches around the register buffers)
     const size_t adv = (size_t)(kt + 1 < nk ? kt + 1 : kt) * BK;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < CPT; ++j) {
       ra[j] = *(const PE_GLOBAL u32x4*)(pP + adv + j * jstride);
       rb[j] = *(const PE_GLOBAL u32x4*)(pQ + adv + j * jstride);
     }
-    const char* cur = smem + (kt & 1) * 2 * kOpBytes;
-    mma_stage<T>(cur, cur + kOpBytes, wm, wn, lane, acc);
-    char* nxt = smem + ((kt + 1) & 1) * 2 * kOpBytes;
+    const char* cur = smem + (kt & 1) * 2 * C::OPB;
+    mma_stage<T, BT>(cur, cur + C::OPB, wm, wn, lane, acc);
+    char* nxt = smem + ((kt + 1) & 1) * 2 * C::OPB;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < CPT; ++j) {
       *(u32x4*)(nxt + soff + j * 32 * kRowBytes) = ra[j];
-      *(u32x4*)(nxt + kOpBytes + soff + j * 32 * kRowBytes) = rb[j];
+      *(u32x4*)(nxt + C::OPB + soff + j * 32 * kRowBytes) = rb[j];
     }
     __syncthreads();
   }
@@ -344,13 +379,34 @@ __device__ __forceinline__ void wave_amax_atomic(float v, float* slot) {
   if ((threadIdx.x & 63) == 0) atomicMax((unsigned int*)slot, __float_as_uint(v));
 }
 
+__device__ __forceinline__ uint2 pack4_bf16(const float (&v)[4]) {
+  uint2 pk;
+  pk.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+  pk.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+  return pk;
+}
+
 // ------------------------------------------------------------- epilogues
-// Element (fm, fn, r) of the accumulator is C[row][col] with
-// row = wm*64 + fm*16 + 4*(lane/16) + r, col = wn*64 + fn*16 + lane%16.
-template <int P>
+// Accumulator element (fm, fn, g, r) is C[row][col] of the block tile with
+//   F = 16: row = wm*BT/2 + fm*16 + 4*(lane/16) + r,           col = wn*BT/2 + fn*16 + lane%16
+//   F = 32: row = wm*BT/2 + fm*32 + 8*g + 4*(lane/32) + r,     col = wn*BT/2 + fn*32 + lane%32
+// with acc register index 4*g + r; each (fm, fn, g) is four consecutive rows.
+template <int BT>
+__device__ __forceinline__ int acc_row(int wm, int fm, int g, int lane) {
+  constexpr int F = TileCfg<BT>::F;
+  return F == 16 ? wm * (BT / 2) + fm * 16 + 4 * (lane >> 4)
+                 : wm * (BT / 2) + fm * 32 + 8 * g + 4 * (lane >> 5);
+}
+template <int BT>
+__device__ __forceinline__ int acc_col(int wn, int fn, int lane) {
+  constexpr int F = TileCfg<BT>::F;
+  return wn * (BT / 2) + fn * F + (lane % F);
+}
+
+template <int P, int BT, typename A>
 __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, int kind, int ti,
-                                         int tj, const f32x4 (&acc)[4][4]) {
-  using T = typename std::conditional<P == kF32, float, uint16_t>::type;
+                                         int tj, const A (&acc)[4][4]) {
+  typedef TileCfg<BT> C;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const size_t sp = d.sp;
@@ -366,42 +422,35 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
   for (int fm = 0; fm < 4; ++fm) {
 #pragma unroll
     for (int fn = 0; fn < 4; ++fn) {
-      const int i = ti * kTile + wm * 64 + fm * 16 + 4 * (lane >> 4);
-      const int j = tj * kTile + wn * 64 + fn * 16 + (lane & 15);
-      float v[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const size_t o = (size_t)(i + r) * sp + j;
-        if (kind == KIND_GRAM) {
-          v[r] = alpha * acc[fm][fn][r];
-          d.Af[o] = v[r];
-          if (P != kF32) ((uint16_t*)d.As)[o] = f2bf(v[r]);
-          amax = fmaxf(amax, fabsf(v[r]));
-        } else {
-          v[r] = b * d.Af[o] + c * acc[fm][fn][r];
-          if (P == kF32) ((float*)d.Bs)[o] = v[r];
-          else ((uint16_t*)d.Bs)[o] = f2bf(v[r]);
-        }
-      }
-      if (ti != tj) {
-        // mirrored tile: rows j, columns i..i+3 (contiguous)
-        const size_t o = (size_t)j * sp + i;
-        if (kind == KIND_GRAM) {
-          *(float4*)(d.Af + o) = make_float4(v[0], v[1], v[2], v[3]);
-          if (P != kF32) {
-            uint2 pk;
-            pk.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-            pk.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-            *(uint2*)((uint16_t*)d.As + o) = pk;
-          }
-        } else {
-          if (P == kF32) {
-            *(float4*)((float*)d.Bs + o) = make_float4(v[0], v[1], v[2], v[3]);
+      for (int g = 0; g < C::RG; ++g) {
+        const int i = ti * BT + acc_row<BT>(wm, fm, g, lane);
+        const int j = tj * BT + acc_col<BT>(wn, fn, lane);
+        float v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const size_t o = (size_t)(i + r) * sp + j;
+          const float x = acc[fm][fn][4 * g + r];
+          if (kind == KIND_GRAM) {
+            v[r] = alpha * x;
+            d.Af[o] = v[r];
+            if (P != kF32) ((uint16_t*)d.As)[o] = f2bf(v[r]);
+            amax = fmaxf(amax, fabsf(v[r]));
           } else {
-            uint2 pk;
-            pk.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-            pk.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-            *(uint2*)((uint16_t*)d.Bs + o) = pk;
+            v[r] = b * d.Af[o] + c * x;
+            if (P == kF32) ((float*)d.Bs)[o] = v[r];
+            else ((uint16_t*)d.Bs)[o] = f2bf(v[r]);
+          }
+        }
+        if (ti != tj) {
+          // mirrored tile: row j, columns i..i+3 (contiguous)
+          const size_t o = (size_t)j * sp + i;
+          if (kind == KIND_GRAM) {
+            *(float4*)(d.Af + o) = make_float4(v[0], v[1], v[2], v[3]);
+            if (P != kF32) *(uint2*)((uint16_t*)d.As + o) = pack4_bf16(v);
+          } else {
+            if (P == kF32) *(float4*)((float*)d.Bs + o) = make_float4(v[0], v[1], v[2], v[3]);
+            else *(uint2*)((uint16_t*)d.Bs + o) = pack4_bf16(v);
           }
         }
       }
@@ -410,9 +459,10 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
   if (kind == KIND_GRAM && P == kFP8) wave_amax_atomic(amax, d.scal + kScAmaxA + args.t);
 }
 
-template <int P>
+template <int P, int BT, bool LAST, typename A>
 __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, int tm, int tn,
-                                           const f32x4 (&acc)[4][4]) {
+                                           const A (&acc)[4][4]) {
+  typedef TileCfg<BT> C;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   float a, b, c;
@@ -425,66 +475,66 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
   for (int fm = 0; fm < 4; ++fm) {
 #pragma unroll
     for (int fn = 0; fn < 4; ++fn) {
-      const int i = tm * kTile + wm * 64 + fm * 16 + 4 * (lane >> 4);
-      const int n = tn * kTile + wn * 64 + fn * 16 + (lane & 15);
-      float v[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const size_t o = (size_t)(i + r) * Lp + n;
-        v[r] = alpha * (a * d.Xf[o] + acc[fm][fn][r]);
-      }
-      if (!args.last) {
+      for (int g = 0; g < C::RG; ++g) {
+        const int i = tm * BT + acc_row<BT>(wm, fm, g, lane);
+        const int n = tn * BT + acc_col<BT>(wn, fn, lane);
+        float v[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const size_t o = (size_t)(i + r) * Lp + n;
-          d.Xf[o] = v[r];
-          if (P != kF32) ((uint16_t*)d.Xb)[o] = f2bf(v[r]);
-          amax = fmaxf(amax, fabsf(v[r]));
+          v[r] = alpha * (a * d.Xf[o] + acc[fm][fn][4 * g + r]);
         }
-        const size_t ot = (size_t)n * sp + i;
-        if (P == kF32) {
-          *(float4*)((float*)XTn + ot) = make_float4(v[0], v[1], v[2], v[3]);
-        } else {
-          uint2 pk;
-          pk.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-          pk.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-          *(uint2*)((uint16_t*)XTn + ot) = pk;
-        }
-      } else if (n < d.L) {
+        if constexpr (!LAST) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if (i + r >= d.s) break;
-          const size_t o = d.trans ? (size_t)n * d.ldo + (i + r) : (size_t)(i + r) * d.ldo + n;
-          if (d.out_bf16) ((uint16_t*)d.Out)[o] = f2bf(v[r]);
-          else ((float*)d.Out)[o] = v[r];
+          for (int r = 0; r < 4; ++r) {
+            const size_t o = (size_t)(i + r) * Lp + n;
+            d.Xf[o] = v[r];
+            if (P != kF32) ((uint16_t*)d.Xb)[o] = f2bf(v[r]);
+            amax = fmaxf(amax, fabsf(v[r]));
+          }
+          const size_t ot = (size_t)n * sp + i;
+          if (P == kF32) *(float4*)((float*)XTn + ot) = make_float4(v[0], v[1], v[2], v[3]);
+          else *(uint2*)((uint16_t*)XTn + ot) = pack4_bf16(v);
+        } else if (n < d.L) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (i + r < d.s) {
+              const size_t o = d.trans ? (size_t)n * d.ldo + (i + r) : (size_t)(i + r) * d.ldo + n;
+              if (d.out_bf16) ((uint16_t*)d.Out)[o] = f2bf(v[r]);
+              else ((float*)d.Out)[o] = v[r];
+            }
+          }
         }
       }
     }
   }
-  if (!args.last && args.fp8_next) wave_amax_atomic(amax, d.scal + kScAmaxX + args.t + 1);
+  if (!LAST && args.fp8_next) wave_amax_atomic(amax, d.scal + kScAmaxX + args.t + 1);
 }
 
 // ------------------------------------------------------------- kernels
-template <int P, int KIND>
-__global__ __launch_bounds__(kThreads, 2) void gemm_kernel(KArgs args) {
+template <int P, int KIND, int BT>
+__global__ __launch_bounds__(kThreads, BT == 128 ? 2 : 1) void gemm_kernel(KArgs args) {
   using T = typename std::conditional<P == kF32, float, uint16_t>::type;
+  typedef TileCfg<BT> C;
+  typedef typename AccT<C::ACC>::type Acc;
   constexpr int BK = OpT<T>::kBK;
-  __shared__ __attribute__((aligned(16))) char smem[4 * kOpBytes];
+  __shared__ __attribute__((aligned(16))) char smem[C::LDS];
   for (int item = blockIdx.x; item < args.total; item += gridDim.x) {
     const int mi = find_mat(args.offs, args.count, item);
     const MatDesc& d = args.descs[mi];
     const int local = item - args.offs[mi];
-    f32x4 acc[4][4];
+    Acc acc[4][4];
 #pragma unroll
     for (int fm = 0; fm < 4; ++fm)
 #pragma unroll
-      for (int fn = 0; fn < 4; ++fn) acc[fm][fn] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (KIND == KIND_UPD) {
+      for (int fn = 0; fn < 4; ++fn) acc[fm][fn] = Acc{};
+    if constexpr (KIND == KIND_UPD || KIND == KIND_UPD_LAST) {
       const int tm = local % d.nb, tn = local / d.nb;
       const T* Bop = (const T*)d.Bs;
       const T* XTc = (const T*)((args.t & 1) ? d.XT1 : d.XT0);
-      gemm_nt_tile<T>(Bop, XTc, d.sp, tm * kTile, tn * kTile, 0, d.sp, smem, acc);
-      epi_update<P>(args, d, tm, tn, acc);
+      gemm_nt_tile<T, BT>(Bop, XTc, d.sp, tm * BT, tn * BT, 0, d.sp, smem, acc);
+      epi_update<P, BT, KIND == KIND_UPD_LAST>(args, d, tm, tn, acc);
     } else {
       const int split = KIND == KIND_GRAM ? d.gram_split : d.a2_split;
       const int tile = local / split, ksp = local % split;
@@ -501,25 +551,34 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(KArgs args) {
       }
       int k0, k1;
       split_range(K, split, ksp, BK, &k0, &k1);
-      if (k1 > k0) gemm_nt_tile<T>(Op, Op, K, ti * kTile, tj * kTile, k0, k1, smem, acc);
+      if (k1 > k0) gemm_nt_tile<T, BT>(Op, Op, K, ti * BT, tj * BT, k0, k1, smem, acc);
       if (split == 1) {
-        epi_syrk<P>(args, d, KIND, ti, tj, acc);
+        epi_syrk<P, BT>(args, d, KIND, ti, tj, acc);
       } else {
-        float4* part = (float4*)d.part + ((size_t)(tile * split + ksp) * 16) * kThreads;
+        // partial tile: float4 q of thread t at ((tile*split + ksp)*Q + q)*256 + t
+        constexpr int Q = 16 * C::ACC / 4;
+        float4* part = (float4*)d.part + ((size_t)(tile * split + ksp) * Q) * kThreads;
 #pragma unroll
         for (int fm = 0; fm < 4; ++fm)
 #pragma unroll
-          for (int fn = 0; fn < 4; ++fn) {
-            const f32x4 v = acc[fm][fn];
-            part[(fm * 4 + fn) * kThreads + threadIdx.x] = make_float4(v[0], v[1], v[2], v[3]);
-          }
+          for (int fn = 0; fn < 4; ++fn)
+#pragma unroll
+            for (int g = 0; g < C::ACC / 4; ++g) {
+              const int q = (fm * 4 + fn) * (C::ACC / 4) + g;
+              part[q * kThreads + threadIdx.x] =
+                  make_float4(acc[fm][fn][4 * g], acc[fm][fn][4 * g + 1], acc[fm][fn][4 * g + 2],
+                              acc[fm][fn][4 * g + 3]);
+            }
       }
     }
   }
 }
 
-template <int P, int KIND>
+template <int P, int KIND, int BT>
 __global__ __launch_bounds__(kThreads) void splitk_reduce_kernel(KArgs args) {
+  typedef TileCfg<BT> C;
+  typedef typename AccT<C::ACC>::type Acc;
+  constexpr int Q = 16 * C::ACC / 4;
   for (int item = blockIdx.x; item < args.total; item += gridDim.x) {
     const int mi = find_mat(args.offs, args.count, item);
     const MatDesc& d = args.descs[mi];
@@ -527,18 +586,26 @@ __global__ __launch_bounds__(kThreads) void splitk_reduce_kernel(KArgs args) {
     const int split = KIND == KIND_GRAM ? d.gram_split : d.a2_split;
     int ti, tj;
     tri_decode(tile, d.nb, &ti, &tj);
-    f32x4 acc[4][4];
-    const float4* part = (const float4*)d.part + ((size_t)tile * split * 16) * kThreads;
+    Acc acc[4][4];
+    const float4* part = (const float4*)d.part + ((size_t)tile * split * Q) * kThreads;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      float4 s = part[q * kThreads + threadIdx.x];
-      for (int k = 1; k < split; ++k) {
-        const float4 p = part[((size_t)k * 16 + q) * kThreads + threadIdx.x];
-        s.x += p.x; s.y += p.y; s.z += p.z; s.w += p.w;
-      }
-      acc[q >> 2][q & 3] = f32x4{s.x, s.y, s.z, s.w};
-    }
-    epi_syrk<P>(args, d, KIND, ti, tj, acc);
+    for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < 4; ++fn)
+#pragma unroll
+        for (int g = 0; g < C::ACC / 4; ++g) {
+          const int q = (fm * 4 + fn) * (C::ACC / 4) + g;
+          float4 s = part[q * kThreads + threadIdx.x];
+          for (int k = 1; k < split; ++k) {
+            const float4 p = part[((size_t)k * Q + q) * kThreads + threadIdx.x];
+            s.x += p.x; s.y += p.y; s.z += p.z; s.w += p.w;
+          }
+          acc[fm][fn][4 * g] = s.x;
+          acc[fm][fn][4 * g + 1] = s.y;
+          acc[fm][fn][4 * g + 2] = s.z;
+          acc[fm][fn][4 * g + 3] = s.w;
+        }
+    epi_syrk<P, BT>(args, d, KIND, ti, tj, acc);
   }
 }
 
@@ -577,33 +644,47 @@ hipError_t launch_prep(int prec, const KArgs& a, int grid_cap, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_gemm(int prec, int kind, const KArgs& a, int grid_cap, hipStream_t st) {
+template <int P, int BT>
+static void launch_gemm_t(int kind, const KArgs& a, int g, hipStream_t st) {
+  if (kind == KIND_GRAM)
+    hipLaunchKernelGGL((gemm_kernel<P, KIND_GRAM, BT>), dim3(g), dim3(kThreads), 0, st, a);
+  else if (kind == KIND_A2)
+    hipLaunchKernelGGL((gemm_kernel<P, KIND_A2, BT>), dim3(g), dim3(kThreads), 0, st, a);
+  else if (!a.last)
+    hipLaunchKernelGGL((gemm_kernel<P, KIND_UPD, BT>), dim3(g), dim3(kThreads), 0, st, a);
+  else
+    hipLaunchKernelGGL((gemm_kernel<P, KIND_UPD_LAST, BT>), dim3(g), dim3(kThreads), 0, st, a);
+}
+
+template <int P, int BT>
+static void launch_reduce_t(int kind, const KArgs& a, int g, hipStream_t st) {
+  if (kind == KIND_GRAM)
+    hipLaunchKernelGGL((splitk_reduce_kernel<P, KIND_GRAM, BT>), dim3(g), dim3(kThreads), 0, st, a);
+  else
+    hipLaunchKernelGGL((splitk_reduce_kernel<P, KIND_A2, BT>), dim3(g), dim3(kThreads), 0, st, a);
+}
+
+hipError_t launch_gemm(int prec, int bt, int kind, const KArgs& a, int grid_cap, hipStream_t st) {
   const int g = grid_for(a.total, grid_cap);
-#define PE_LAUNCH(P, K) hipLaunchKernelGGL((gemm_kernel<P, K>), dim3(g), dim3(kThreads), 0, st, a)
   if (prec == kF32) {
-    if (kind == KIND_GRAM) PE_LAUNCH(kF32, KIND_GRAM);
-    else if (kind == KIND_A2) PE_LAUNCH(kF32, KIND_A2);
-    else PE_LAUNCH(kF32, KIND_UPD);
+    if (bt == 256) launch_gemm_t<kF32, 256>(kind, a, g, st);
+    else launch_gemm_t<kF32, 128>(kind, a, g, st);
   } else {
-    if (kind == KIND_GRAM) PE_LAUNCH(kBF16, KIND_GRAM);
-    else if (kind == KIND_A2) PE_LAUNCH(kBF16, KIND_A2);
-    else PE_LAUNCH(kBF16, KIND_UPD);
+    if (bt == 256) launch_gemm_t<kBF16, 256>(kind, a, g, st);
+    else launch_gemm_t<kBF16, 128>(kind, a, g, st);
   }
-#undef PE_LAUNCH
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(int prec, int kind, const KArgs& a, int grid_cap, hipStream_t st) {
+hipError_t launch_reduce(int prec, int bt, int kind, const KArgs& a, int grid_cap, hipStream_t st) {
   const int g = grid_for(a.total, grid_cap);
-#define PE_LAUNCH(P, K) hipLaunchKernelGGL((splitk_reduce_kernel<P, K>), dim3(g), dim3(kThreads), 0, st, a)
   if (prec == kF32) {
-    if (kind == KIND_GRAM) PE_LAUNCH(kF32, KIND_GRAM);
-    else PE_LAUNCH(kF32, KIND_A2);
+    if (bt == 256) launch_reduce_t<kF32, 256>(kind, a, g, st);
+    else launch_reduce_t<kF32, 128>(kind, a, g, st);
   } else {
-    if (kind == KIND_GRAM) PE_LAUNCH(kBF16, KIND_GRAM);
-    else PE_LAUNCH(kBF16, KIND_A2);
+    if (bt == 256) launch_reduce_t<kBF16, 256>(kind, a, g, st);
+    else launch_reduce_t<kBF16, 128>(kind, a, g, st);
   }
-#undef PE_LAUNCH
   return hipGetLastError();
 }
 

@@ -4,7 +4,7 @@
 // workspace).  The iterate is oriented as X = G (m <= n) or X = G^T (m > n),
 // so X is s x L with s = min(m, n) <= L = max(m, n) and the Gram matrix is
 // s x s (the smaller side).  s and L are padded with zeros to sp, Lp
-// (multiples of 128).  Zero rows/columns stay exactly zero under
+// (multiples of the block tile, 128 or 256).  Zero rows/columns stay exactly zero under
 // X <- aX + (bA + cA^2)X, so every kernel runs on the padded shape with no
 // bounds checks; only the input read and the final store see m, n.
 //   Xf      sp x Lp  fp32   master iterate (row-major)
@@ -21,8 +21,8 @@
 
 namespace pe {
 
-constexpr int kTile = 128;      // GEMM block tile (M = N = 128)
-constexpr int kPad = 128;       // padding of s and L
+constexpr int kTileSmall = 128; // GEMM block tiles: 128 x 128 or 256 x 256
+constexpr int kTileLarge = 256;
 constexpr int kPrepTile = 64;   // norm/prep tile
 constexpr int kThreads = 256;   // threads per block (4 wave64)
 constexpr int kMaxSteps = 64;
@@ -58,7 +58,7 @@ struct MatDesc {
   float* scal;      // [kScN]
   uint32_t* cnt;    // [4]
   int32_t n_prep, syrk_nt, upd_nt, gram_split;
-  int32_t a2_split, pad0, pad1, pad2;
+  int32_t a2_split, bt, pad1, pad2;  // bt: block tile edge
 };
 
 struct KArgs {

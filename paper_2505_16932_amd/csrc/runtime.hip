@@ -22,8 +22,8 @@ namespace pe {
 hipError_t launch_put(const PutChunk& c, hipStream_t st);
 hipError_t launch_init(const MatDesc* descs, int count, hipStream_t st);
 hipError_t launch_prep(int prec, const KArgs& a, int grid_cap, hipStream_t st);
-hipError_t launch_gemm(int prec, int kind, const KArgs& a, int grid_cap, hipStream_t st);
-hipError_t launch_reduce(int prec, int kind, const KArgs& a, int grid_cap, hipStream_t st);
+hipError_t launch_gemm(int prec, int bt, int kind, const KArgs& a, int grid_cap, hipStream_t st);
+hipError_t launch_reduce(int prec, int bt, int kind, const KArgs& a, int grid_cap, hipStream_t st);
 }  // namespace pe
 
 using namespace pe;
@@ -34,7 +34,8 @@ thread_local std::string g_last_error;
 
 enum Phase { PH_PREP = 0, PH_GRAM, PH_A2, PH_UPD, PH_RGRAM, PH_RA2, PH_N };
 
-constexpr int kGemmGridCap = 512;    // 2 resident blocks per CU x 256 CUs
+constexpr int kGemmGridCap = 512;       // 128-tile kernel: 2 resident blocks per CU x 256 CUs
+constexpr int kGemmGridCapLarge = 256;  // 256-tile kernel: 1 resident block per CU
 constexpr int kPrepGridCap = 2048;
 constexpr int kReduceGridCap = 1024;
 constexpr int kFillTarget = 512;     // Gram-side items wanted per launch
@@ -55,6 +56,7 @@ struct Layout {
   int32_t totals[PH_N] = {0};
   size_t bytes = 0;
   size_t descs_off = 0, offs_off = 0;
+  int bt = kTileSmall;
 };
 
 bool valid_matrix(const pe_matrix& m) {
@@ -84,11 +86,34 @@ pe_status check_opts(const pe_opts* o) {
 
 int prec_of(const pe_opts* o) { return o->compute == PE_COMPUTE_F32 ? kF32 : kBF16; }
 
+// Block tile for a call: 256 x 256 (32x32 MFMA fragments, wave tile 128 x 128)
+// halves the LDS and L2 traffic per flop of the 128 x 128 tile, but pads s and
+// L to multiples of 256 and yields 4x fewer tiles.  Used on the bf16 paths when
+// every matrix has s >= 512 and the update has at least one tile per CU.
+int choose_tile(int count, const pe_matrix* mats, const pe_opts* o) {
+  if (o->tile == 1) return kTileSmall;
+  if (o->tile == 2) return kTileLarge;
+  if (prec_of(o) == kF32) return kTileSmall;
+  int64_t upd_tiles = 0;
+  bool any = false;
+  for (int i = 0; i < count; ++i) {
+    const pe_matrix& m = mats[i];
+    if (m.m <= 0 || m.n <= 0) continue;
+    any = true;
+    const int64_t s = std::min(m.m, m.n), L = std::max(m.m, m.n);
+    if (s < 512) return kTileSmall;
+    upd_tiles += round_up(s, kTileLarge) / kTileLarge * (round_up(L, kTileLarge) / kTileLarge);
+  }
+  return (any && upd_tiles >= 256) ? kTileLarge : kTileSmall;
+}
+
 // Build the per-matrix descriptors and the item tables.  With ws == nullptr
 // only sizes are computed.
 pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char* ws, Layout* L) {
   const int prec = prec_of(o);
   const size_t esz = prec == kF32 ? 4 : 2;
+  const int bt = choose_tile(count, mats, o);
+  L->bt = bt;
   L->descs.clear();
   for (int p = 0; p < PH_N; ++p) L->offs[p].assign(1, 0);
   // first pass: shapes and Gram-side tile counts (for the split-K choice)
@@ -101,10 +126,10 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
     if (m.m > 0 && m.n > 0) {
       q.s = std::min(m.m, m.n);
       q.L = std::max(m.m, m.n);
-      q.sp = round_up(q.s, kPad);
-      q.Lp = round_up(q.L, kPad);
-      q.nb = (int)(q.sp / kTile);
-      q.nbL = (int)(q.Lp / kTile);
+      q.sp = round_up(q.s, bt);
+      q.Lp = round_up(q.L, bt);
+      q.nb = (int)(q.sp / bt);
+      q.nbL = (int)(q.Lp / bt);
       q.syrk = q.nb * (q.nb + 1) / 2;
       q.upd = q.nb * q.nbL;
       q.prep = (int)((q.sp / kPrepTile) * (q.Lp / kPrepTile));
@@ -138,6 +163,7 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
     d.out_bf16 = m.x_dtype == PE_BF16;
     d.nb = q.nb;
     d.nbL = q.nbL;
+    d.bt = bt;
     d.n_prep = q.prep;
     d.syrk_nt = q.syrk;
     d.upd_nt = q.upd;
@@ -162,7 +188,7 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
       d.As = prec == kF32 ? (void*)d.Af : take(A * 2);
       d.Bs = take(A * esz);
       const int split = std::max(d.gram_split, d.a2_split);
-      d.part = split > 1 ? (float*)take((size_t)q.syrk * split * kTile * kTile * 4) : nullptr;
+      d.part = split > 1 ? (float*)take((size_t)q.syrk * split * bt * bt * 4) : nullptr;
       d.red = (double*)take((size_t)q.prep * 12 + 16);
       d.scal = (float*)take(kScN * 4);
       d.cnt = (uint32_t*)take(64);
@@ -280,11 +306,11 @@ pe_status enqueue_gemm(const pe_plan* p, int t, int kind, hipStream_t st) {
   KArgs a = base_args(p);
   set_step(p, &a, t);
   set_phase(p, &a, ph_main[kind]);
-  hipError_t e = launch_gemm(p->prec, kind, a, kGemmGridCap, st);
+  hipError_t e = launch_gemm(p->prec, p->L.bt, kind, a, p->L.bt == kTileLarge ? kGemmGridCapLarge : kGemmGridCap, st);
   if (e != hipSuccess) return hip_fail(e, names[kind]);
   if (ph_red[kind] >= 0 && p->L.totals[ph_red[kind]]) {
     set_phase(p, &a, ph_red[kind]);
-    if ((e = launch_reduce(p->prec, kind, a, kReduceGridCap, st)) != hipSuccess)
+    if ((e = launch_reduce(p->prec, p->L.bt, kind, a, kReduceGridCap, st)) != hipSuccess)
       return hip_fail(e, "split-k reduce");
   }
   return PE_OK;
@@ -410,10 +436,15 @@ pe_status pe_plan_destroy(pe_plan* p) {
   return PE_OK;
 }
 
-int32_t pe_tile_count(void) { return 1; }
+int32_t pe_tile_count(void) { return 3; }
 
 const char* pe_tile_name(int32_t tile_id) {
-  return tile_id == 0 ? "mfma16_bm128_bn128_w2x2" : nullptr;
+  switch (tile_id) {
+    case 0: return "auto";
+    case 1: return "bt128_w2x2_mfma16";
+    case 2: return "bt256_w2x2_mfma32";
+  }
+  return nullptr;
 }
 
 pe_status pe_tile_table_load(const char* path) {

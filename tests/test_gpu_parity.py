@@ -213,3 +213,29 @@ def test_loguniform_4096x1024_bf16(pe, torch_cuda):
         print(f"[config2] T={T} relF={err:.3e} polar_err_gpu={polar_error(Xn, P):.4f} "
               f"polar_err_fp64={polar_error(ref, P):.4f}", flush=True)
         assert err <= 3e-2
+
+
+@pytest.mark.parametrize("shape", [(512, 512), (600, 1000), (1000, 600), (768, 2304), (520, 3000)])
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_large_tile_path(pe, torch_cuda, shape, compute):
+    """The 256 x 256 block tile (32x32 MFMA fragments, s and L padded to 256)."""
+    G64 = synth.powerlaw(900 + shape[0] + shape[1], shape[0], shape[1]).G
+    dtype = torch_cuda.float32 if compute == "f32" else torch_cuda.bfloat16
+    _check(pe, torch_cuda, G64, 5, compute, dtype, tile=2)
+
+
+@pytest.mark.parametrize("tile", [1, 2])
+def test_large_tile_split_k(pe, torch_cuda, tile):
+    """One 256-wide Gram tile with a long k range: split-K and its reduction."""
+    G64 = synth.powerlaw(950 + tile, 256, 12000).G
+    _check(pe, torch_cuda, G64, 5, "bf16", torch_cuda.bfloat16, tile=tile)
+
+
+def test_tiles_agree(pe, torch_cuda):
+    """Both block tiles compute the same iteration (up to summation order)."""
+    G64 = synth.powerlaw(960, 768, 1536).G
+    G, vals = device_input(G64, torch_cuda.bfloat16)
+    X1 = pe.polar(G, T=5, compute="bf16", out_dtype=torch_cuda.float32, tile=1)
+    X2 = pe.polar(G, T=5, compute="bf16", out_dtype=torch_cuda.float32, tile=2)
+    torch_cuda.cuda.synchronize()
+    assert relf(to_np(X2), to_np(X1)) <= 2e-2
