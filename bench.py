@@ -9,6 +9,7 @@ Workloads:
   wide-batch        32-layer 4096-wide model: per layer four 4096x4096 and three
                     4096x14336 bf16 matrices (224), sigma_i = 1/i, Haar singular
                     vectors, T = 5                                   (default)
+  wide-layer        one layer of the above (7 matrices), for profiler runs
   gpt-small-batch   12 layers x {768x2304, 768x768, 768x3072, 3072x768} (48), sigma_i = 1/i
   single-4096x1024  one 4096x1024 bf16 matrix, log-uniform spectrum
 
@@ -51,13 +52,26 @@ def update_flops(shapes):
     return sum(2.0 * min(m, n) ** 2 * max(m, n) for m, n in shapes)
 
 
-def make_workload(name, torch, device):
+def make_workload(name, torch, device, inputs="spectral"):
     import synth
+    if inputs == "gaussian":
+        # iid N(0,1) entries of the same shapes: no QR, for profiler runs only
+        # (kernel time does not depend on the spectrum)
+        shapes = {"wide-batch": synth.WIDE_LAYER_SHAPES * 32, "wide-layer": synth.WIDE_LAYER_SHAPES,
+                  "gpt-small-batch": synth.GPT_SMALL_SHAPES * 12, "single-4096x1024": [(4096, 1024)]}[name]
+        g = torch.Generator(device=device)
+        g.manual_seed(7)
+        Gs = [torch.randn(s, generator=g, device=device, dtype=torch.float32).to(torch.bfloat16)
+              for s in shapes]
+        return Gs, 5, dict(gaussian=True)
     if name == "wide-batch":
         mats, templates = synth.torch_layer_batch(32, seed=1004, device=device)
         Gs = [m[0] for m in mats]
         meta = dict(mats=mats, templates=templates)
         return Gs, 5, meta
+    if name == "wide-layer":
+        mats, templates = synth.torch_layer_batch(1, seed=1004, device=device)
+        return [m[0] for m in mats], 5, dict(mats=mats, templates=templates)
     if name == "gpt-small-batch":
         mats, templates = synth.torch_layer_batch(12, seed=1003, device=device,
                                                   shapes=synth.GPT_SMALL_SHAPES)
@@ -117,7 +131,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="wide-batch",
-                    choices=["wide-batch", "gpt-small-batch", "single-4096x1024"])
+                    choices=["wide-batch", "wide-layer", "gpt-small-batch", "single-4096x1024"])
     ap.add_argument("--compute", default="bf16", choices=["bf16", "fp8", "f32"])
     ap.add_argument("--fp8-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -125,6 +139,8 @@ def main():
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--phase-reps", type=int, default=10)
     ap.add_argument("--tile", type=int, default=0, help="0 auto, 1 = 128x128, 2 = 256x256 block tile")
+    ap.add_argument("--inputs", default="spectral", choices=["spectral", "gaussian"],
+                    help="gaussian: iid inputs of the same shapes (profiler runs; no polar error)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -142,7 +158,7 @@ def main():
     pe.lib()
     log(f"[bench] generating workload {args.workload}")
     t0 = time.perf_counter()
-    Gs, T, meta = make_workload(args.workload, torch, dev)
+    Gs, T, meta = make_workload(args.workload, torch, dev, args.inputs)
     torch.cuda.synchronize()
     log(f"[bench] {len(Gs)} matrices ready in {time.perf_counter() - t0:.1f} s")
     shapes = [tuple(G.shape) for G in Gs]
@@ -188,7 +204,7 @@ def main():
     torch.cuda.synchronize()
 
     extra = {}
-    if not args.no_error:
+    if not args.no_error and "gaussian" not in meta:
         errs = []
         for idx in sorted(set([0, min(4, len(Gs) - 1)])):
             P = polar_factor(meta, idx, torch).float()

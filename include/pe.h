@@ -150,6 +150,15 @@ pe_status pe_plan_destroy(pe_plan* plan);
  * step = T-1 and phase = 3.  PE_EINVAL for a bad step or phase. */
 pe_status pe_plan_launch_phase(pe_plan* plan, int32_t step, int32_t phase, void* stream);
 
+/* The e4m3 conversion of the FP8 path, for checking it: q[i] = e4m3(x[i] * scale)
+ * (OCP E4M3, round to nearest even; |x[i] * scale| must not exceed 448, which the
+ * FP8 path guarantees by choosing scale as the largest power of two with
+ * 1.01 * max|x| * scale <= 448).  x: device, n elements of x_dtype; q: device,
+ * n bytes.  Asynchronous on `stream`.  PE_EINVAL for bad pointers, n < 0, or a
+ * non-positive or non-finite scale. */
+pe_status pe_quantize_e4m3(const void* x, int32_t x_dtype, void* q, int64_t n, float scale,
+                           void* stream);
+
 /* Tile configurations compiled into the library and the autotuned table.
  * pe_tile_table_load reads a text table "<shape-class> <tile-id>" per line
  * (written by the autotuner); it replaces the built-in choices. */

@@ -99,6 +99,9 @@ def lib() -> ctypes.CDLL:
                                            ctypes.c_void_p]
         L.pe_plan_destroy.restype = ctypes.c_int
         L.pe_plan_destroy.argtypes = [ctypes.c_void_p]
+        L.pe_quantize_e4m3.restype = ctypes.c_int
+        L.pe_quantize_e4m3.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                       ctypes.c_int64, ctypes.c_float, ctypes.c_void_p]
         L.pe_tile_count.restype = ctypes.c_int32
         L.pe_tile_name.restype = ctypes.c_char_p
         L.pe_tile_name.argtypes = [ctypes.c_int32]
@@ -247,6 +250,17 @@ def polar_batched(Gs, T: int = 5, ell: float = 1e-3, abc=None, compute: str = "b
         # keep the workspace alive until the stream has consumed it
         ws_buf.record_stream(torch.cuda.current_stream() if stream is None else stream)
     return outs
+
+
+def quantize_e4m3(x, scale: float, stream=None):
+    """e4m3 bytes of x * scale with the FP8 path's device conversion."""
+    import torch
+    x = x.contiguous().view(-1)
+    q = torch.empty(x.numel(), dtype=torch.uint8, device=x.device)
+    _check(lib().pe_quantize_e4m3(ctypes.c_void_p(x.data_ptr()), _dtype_code(x.dtype),
+                                  ctypes.c_void_p(q.data_ptr()), x.numel(), float(scale),
+                                  _stream(stream)), "pe_quantize_e4m3")
+    return q
 
 
 class Plan:

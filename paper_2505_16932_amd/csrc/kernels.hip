@@ -80,14 +80,72 @@ __device__ __forceinline__ void step_coef(const KArgs& args, const MatDesc& d, f
 }
 
 // ------------------------------------------------------------------ prep
-// One 64x64 tile of the oriented, padded X per iteration of the block loop.
+// One 64 x 64 tile of the oriented, padded X per iteration of the block loop.
+// Thread t owns two 8-element row chunks of the source block (rows t/8 and
+// t/8 + 32, columns 8*(t%8)..+8) and, after an LDS transpose, the matching
+// chunks of the transposed block.  Each tile writes its own partial sum of
+// squares (FP64) and max |G|; finalize_kernel reduces them in fixed order.
+__device__ __forceinline__ void load8(const MatDesc& d, int gr, int gc, int srn, int scn, float (&v)[8]) {
+  if (gr < srn && d.g_vec && gc + 8 <= scn) {
+    const size_t off = (size_t)gr * d.ldg + gc;
+    if (d.g_bf16) {
+      const u32x4 c = *(const PE_GLOBAL u32x4*)(gview((const uint16_t*)d.G) + off);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        v[2 * e] = __uint_as_float(c[e] << 16);
+        v[2 * e + 1] = __uint_as_float(c[e] & 0xffff0000u);
+      }
+    } else {
+      const PE_GLOBAL f32x4* q = (const PE_GLOBAL f32x4*)(gview((const float*)d.G) + off);
+      const f32x4 c0 = q[0], c1 = q[1];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) { v[e] = c0[e]; v[4 + e] = c1[e]; }
+    }
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    float x = 0.0f;
+    if (gr < srn && gc + e < scn) {
+      const size_t off = (size_t)gr * d.ldg + gc + e;
+      x = d.g_bf16 ? bf2f(((const uint16_t*)d.G)[off]) : ((const float*)d.G)[off];
+    }
+    v[e] = x;
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void store8_f32(float* dst, const float (&v)[8]) {
+  *(f32x4*)dst = f32x4{v[0], v[1], v[2], v[3]};
+  *(f32x4*)(dst + 4) = f32x4{v[4], v[5], v[6], v[7]};
+}
+__device__ __forceinline__ void store8_bf16(uint16_t* dst, const float (&v)[8]) {
+  u32x4 w;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) w[e] = (uint32_t)f2bf(v[2 * e]) | ((uint32_t)f2bf(v[2 * e + 1]) << 16);
+  *(u32x4*)dst = w;
+}
+
+// row-major X row chunk: fp32 master and (bf16 paths) the bf16 operand copy
+template <int P>
+__device__ __forceinline__ void store_x_chunk(const MatDesc& d, size_t o, const float (&v)[8]) {
+  store8_f32<P>(d.Xf + o, v);
+  if (P != kF32) store8_bf16((uint16_t*)d.Xb + o, v);
+}
+// X^T row chunk (operand of B X)
+template <int P>
+__device__ __forceinline__ void store_xt_chunk(const MatDesc& d, size_t o, const float (&v)[8]) {
+  if (P == kF32) store8_f32<P>((float*)d.XT0 + o, v);
+  else store8_bf16((uint16_t*)d.XT0 + o, v);
+}
+
 template <int P>
 __global__ __launch_bounds__(kThreads) void prep_kernel(KArgs args) {
   __shared__ float tile[kPrepTile][kPrepTile + 1];
   __shared__ double red_d[kThreads / 64];
   __shared__ float red_f[kThreads / 64];
-  __shared__ int last_flag;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rr = tid >> 3, cc = (tid & 7) * 8;
   for (int item = blockIdx.x; item < args.total; item += gridDim.x) {
     const int mi = find_mat(args.offs, args.count, item);
     const MatDesc& d = args.descs[mi];
@@ -95,84 +153,35 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(KArgs args) {
     const int ntk = d.Lp / kPrepTile;
     const int i0 = (local / ntk) * kPrepTile;   // rows of X (s side)
     const int k0 = (local % ntk) * kPrepTile;   // cols of X (L side)
-    // source block: rows r, cols c of G's own layout
+    // source block in G's own layout
     const int sr0 = d.trans ? k0 : i0, sc0 = d.trans ? i0 : k0;
-    const int srn = d.trans ? d.L : d.s, scn = d.trans ? d.s : d.L;  // valid extents in G layout
+    const int srn = d.trans ? d.L : d.s, scn = d.trans ? d.s : d.L;
     double ss = 0.0;
     float amax = 0.0f;
-    const int cq = (tid & 15) * 4;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = (tid >> 4) + 16 * j;
-      float v[4];
+    for (int j = 0; j < 2; ++j) {
+      const int r = rr + 32 * j;
+      float v[8];
+      load8(d, sr0 + r, sc0 + cc, srn, scn, v);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gr = sr0 + r, gc = sc0 + cq + e;
-        float x = 0.0f;
-        if (gr < srn && gc < scn) {
-          const size_t off = (size_t)gr * d.ldg + gc;
-          x = d.g_bf16 ? bf2f(((const uint16_t*)d.G)[off]) : ((const float*)d.G)[off];
-        }
-        v[e] = x;
-        tile[r][cq + e] = x;
-        ss += (double)x * (double)x;
-        amax = fmaxf(amax, fabsf(x));
+      for (int e = 0; e < 8; ++e) {
+        tile[r][cc + e] = v[e];
+        ss += (double)v[e] * (double)v[e];
+        amax = fmaxf(amax, fabsf(v[e]));
       }
-      // direct output: the buffer whose row layout matches G's
-      if (!d.trans) {
-        const size_t o = (size_t)(i0 + r) * d.Lp + k0 + cq;
-        if (P == kF32) {
-          *(float4*)(d.Xf + o) = make_float4(v[0], v[1], v[2], v[3]);
-        } else {
-          *(float4*)(d.Xf + o) = make_float4(v[0], v[1], v[2], v[3]);
-          uint2 pk;
-          pk.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-          pk.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-          *(uint2*)((uint16_t*)d.Xb + o) = pk;
-        }
-      } else {
-        const size_t o = (size_t)(k0 + r) * d.sp + i0 + cq;
-        if (P == kF32) {
-          *(float4*)((float*)d.XT0 + o) = make_float4(v[0], v[1], v[2], v[3]);
-        } else {
-          uint2 pk;
-          pk.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-          pk.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-          *(uint2*)((uint16_t*)d.XT0 + o) = pk;
-        }
-      }
+      if (!d.trans) store_x_chunk<P>(d, (size_t)(i0 + r) * d.Lp + k0 + cc, v);
+      else store_xt_chunk<P>(d, (size_t)(k0 + r) * d.sp + i0 + cc, v);
     }
     __syncthreads();
-    // transposed output from LDS
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = (tid >> 4) + 16 * j;
-      float v[4];
+    for (int j = 0; j < 2; ++j) {
+      const int q = rr + 32 * j;
+      float v[8];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] = tile[cq + e][r];
-      if (!d.trans) {
-        // XT[k][i]: row k = k0 + r, cols i0 + cq..
-        const size_t o = (size_t)(k0 + r) * d.sp + i0 + cq;
-        if (P == kF32) {
-          *(float4*)((float*)d.XT0 + o) = make_float4(v[0], v[1], v[2], v[3]);
-        } else {
-          uint2 pk;
-          pk.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-          pk.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-          *(uint2*)((uint16_t*)d.XT0 + o) = pk;
-        }
-      } else {
-        const size_t o = (size_t)(i0 + r) * d.Lp + k0 + cq;
-        *(float4*)(d.Xf + o) = make_float4(v[0], v[1], v[2], v[3]);
-        if (P != kF32) {
-          uint2 pk;
-          pk.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-          pk.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-          *(uint2*)((uint16_t*)d.Xb + o) = pk;
-        }
-      }
+      for (int e = 0; e < 8; ++e) v[e] = tile[cc + e][q];
+      if (!d.trans) store_xt_chunk<P>(d, (size_t)(k0 + q) * d.sp + i0 + cc, v);
+      else store_x_chunk<P>(d, (size_t)(i0 + q) * d.Lp + k0 + cc, v);
     }
-    // block reduction of this tile's sum of squares and max, fixed order
     for (int off = 32; off > 0; off >>= 1) {
       ss += __shfl_xor(ss, off);
       amax = fmaxf(amax, __shfl_xor(amax, off));
@@ -180,46 +189,45 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(KArgs args) {
     if (lane == 0) { red_d[wave] = ss; red_f[wave] = amax; }
     __syncthreads();
     if (tid == 0) {
-      const double s4 = (red_d[0] + red_d[1]) + (red_d[2] + red_d[3]);
-      const float a4 = fmaxf(fmaxf(red_f[0], red_f[1]), fmaxf(red_f[2], red_f[3]));
-      d.red[local] = s4;
-      ((float*)(d.red + d.n_prep))[local] = a4;
-      __threadfence();
-      const uint32_t prev = atomicAdd(&d.cnt[0], 1u);
-      last_flag = (prev == (uint32_t)d.n_prep - 1u);
+      d.red[local] = (red_d[0] + red_d[1]) + (red_d[2] + red_d[3]);
+      ((float*)(d.red + d.n_prep))[local] = fmaxf(fmaxf(red_f[0], red_f[1]), fmaxf(red_f[2], red_f[3]));
+    }
+  }
+}
+
+// One block per matrix: fixed-order reduction of the tile partials (the same
+// result for any launch geometry), then sigma = 1 / (1.01 ||G||_F + 1e-7)
+// (or 1 / (||G||_F + 1e-2)); clears the amax slots the FP8 steps accumulate into.
+__global__ __launch_bounds__(kThreads) void finalize_kernel(KArgs args) {
+  __shared__ double red_d[kThreads / 64];
+  __shared__ float red_f[kThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int mi = blockIdx.x; mi < args.count; mi += gridDim.x) {
+    const MatDesc& d = args.descs[mi];
+    if (d.n_prep == 0) continue;
+    double acc = 0.0;
+    float am = 0.0f;
+    const float* rf = (const float*)(d.red + d.n_prep);
+    for (int i = tid; i < d.n_prep; i += kThreads) {
+      acc += d.red[i];
+      am = fmaxf(am, rf[i]);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      acc += __shfl_xor(acc, off);
+      am = fmaxf(am, __shfl_xor(am, off));
     }
     __syncthreads();
-    if (last_flag) {
-      // the block that finished this matrix's last tile reduces all partials
-      __threadfence();
-      double acc = 0.0;
-      float am = 0.0f;
-      const volatile double* rd = d.red;
-      const volatile float* rf = (const volatile float*)(d.red + d.n_prep);
-      for (int i = tid; i < d.n_prep; i += kThreads) {
-        acc += rd[i];
-        am = fmaxf(am, rf[i]);
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        acc += __shfl_xor(acc, off);
-        am = fmaxf(am, __shfl_xor(am, off));
-      }
-      __syncthreads();
-      if (lane == 0) { red_d[wave] = acc; red_f[wave] = am; }
-      __syncthreads();
-      if (tid == 0) {
-        const double tot = (red_d[0] + red_d[1]) + (red_d[2] + red_d[3]);
-        const double fro = sqrt(tot);
-        const double sigma = args.norm_mode == 1 ? 1.0 / (fro + 1e-2) : 1.0 / (1.01 * fro + 1e-7);
-        d.scal[kScScale] = (float)sigma;
-        d.scal[kScAmaxG] = fmaxf(fmaxf(red_f[0], red_f[1]), fmaxf(red_f[2], red_f[3]));
-        d.scal[kScFro] = (float)fro;
-        d.cnt[0] = 0u;
-      }
-      // clear the amax slots the later steps accumulate into
-      for (int i = kScAmaxX + tid; i < kScN; i += kThreads) d.scal[i] = 0.0f;
-    }
+    if (lane == 0) { red_d[wave] = acc; red_f[wave] = am; }
     __syncthreads();
+    if (tid == 0) {
+      const double tot = (red_d[0] + red_d[1]) + (red_d[2] + red_d[3]);
+      const double fro = sqrt(tot);
+      const double sigma = args.norm_mode == 1 ? 1.0 / (fro + 1e-2) : 1.0 / (1.01 * fro + 1e-7);
+      d.scal[kScScale] = (float)sigma;
+      d.scal[kScAmaxG] = fmaxf(fmaxf(red_f[0], red_f[1]), fmaxf(red_f[2], red_f[3]));
+      d.scal[kScFro] = (float)fro;
+    }
+    for (int i = kScAmaxX + tid; i < kScN; i += kThreads) d.scal[i] = 0.0f;
   }
 }
 
@@ -346,6 +354,9 @@ __device__ __forceinline__ void gemm_nt_tile(const T* __restrict__ P, const T* _
       ra[j] = *(const PE_GLOBAL u32x4*)(pP + adv + j * jstride);
       rb[j] = *(const PE_GLOBAL u32x4*)(pQ + adv + j * jstride);
     }
+    // keep the prefetch at the top of the stage: a whole stage of MFMA work
+    // then covers its latency
+    __builtin_amdgcn_sched_barrier(0);
     const char* cur = smem + (kt & 1) * 2 * C::OPB;
     mma_stage<T, BT>(cur, cur + C::OPB, wm, wn, lane, acc);
     char* nxt = smem + ((kt + 1) & 1) * 2 * C::OPB;
@@ -356,6 +367,146 @@ __device__ __forceinline__ void gemm_nt_tile(const T* __restrict__ P, const T* _
     }
     __syncthreads();
   }
+}
+
+// ------------------------------------------------- bf16 direct-to-LDS main loop
+// The bf16 path's main loop.  Operands go from HBM straight into LDS with
+// global_load_lds_dwordx4 (lane i of a wave writes 16 bytes at LDS base + 16 i),
+// so no registers stage them and no wait on a load sits in front of an LDS
+// store.  Stages hold 32 k (64 bytes per row, unpadded) in a ring of four; the
+// loads of stage kt + 3 are in flight while stage kt is multiplied.  A row's
+// four 16-byte chunks are stored XOR-swizzled by (row / 4) % 4, which spreads
+// the fragment reads of consecutive rows over all banks.
+template <int BT>
+struct DlCfg {
+  static constexpr int F = BT / 8;
+  static constexpr int BK = 32;                  // k per stage
+  static constexpr int NS = 4;                   // stages in the LDS ring
+  static constexpr int ROWB = 64;                // bytes per row per stage
+  static constexpr int OPB = BT * ROWB;          // one operand, one stage
+  static constexpr int STB = 2 * OPB;            // one stage
+  static constexpr int LDS = NS * STB;
+  static constexpr int IPW = OPB / 1024 / 4;     // 1-KB loads per wave per operand per stage
+  static constexpr int LPS = 2 * IPW;            // load instructions per wave per stage
+};
+
+__device__ __forceinline__ int dl_swz(int row, int chunk) { return chunk ^ ((row >> 2) & 3); }
+
+// s_waitcnt vmcnt(n) (gfx9 encoding: vmcnt[3:0] | vmcnt[5:4] << 14; exp/lgkm at max)
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+template <int BT>
+__device__ __forceinline__ void dl_issue_stage(const PE_GLOBAL uint16_t* P, const PE_GLOBAL uint16_t* Q,
+                                               int64_t ld, int kofs, char* slot, int wave, int lane) {
+  typedef DlCfg<BT> C;
+#pragma unroll
+  for (int op = 0; op < 2; ++op) {
+    const PE_GLOBAL uint16_t* base = op == 0 ? P : Q;
+#pragma unroll
+    for (int j = 0; j < C::IPW; ++j) {
+      const int blk = wave * C::IPW + j;            // 1-KB block = 16 rows
+      const int row = blk * 16 + (lane >> 2);
+      const int lc = dl_swz(row, lane & 3);          // logical chunk this lane fetches
+      const PE_GLOBAL uint16_t* g = base + (size_t)row * ld + kofs + lc * 8;
+      __builtin_amdgcn_global_load_lds((const void*)g,
+                                       (__attribute__((address_space(3))) void*)(slot + op * C::OPB + blk * 1024),
+                                       16, 0, 0);
+    }
+  }
+}
+
+template <int BT, typename A>
+__device__ __forceinline__ void dl_mma_stage(const char* sA, const char* sB, int wm, int wn, int lane,
+                                             A (&acc)[4][4]) {
+  constexpr int F = BT / 8;
+  constexpr int NSUB = F == 16 ? 1 : 2;          // MFMA k-steps per 32-k stage
+#pragma unroll
+  for (int ks = 0; ks < NSUB; ++ks) {
+    u32x4 fa[4], fb[4];
+    const int lc = F == 16 ? (lane >> 4) : (2 * ks + (lane >> 5));
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const int ra = wm * (BT / 2) + f * F + (lane % F);
+      const int rb = wn * (BT / 2) + f * F + (lane % F);
+      fa[f] = *(const u32x4*)(sA + ra * 64 + dl_swz(ra, lc) * 16);
+      fb[f] = *(const u32x4*)(sB + rb * 64 + dl_swz(rb, lc) * 16);
+    }
+#pragma unroll
+    for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < 4; ++fn) {
+        if constexpr (F == 16)
+          acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              __builtin_bit_cast(bf16x8, fa[fm]), __builtin_bit_cast(bf16x8, fb[fn]), acc[fm][fn], 0, 0, 0);
+        else
+          acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              __builtin_bit_cast(bf16x8, fa[fm]), __builtin_bit_cast(bf16x8, fb[fn]), acc[fm][fn], 0, 0, 0);
+      }
+  }
+}
+
+// acc += P[rp0:+BT, k0:k1] * Q[rq0:+BT, k0:k1]^T (bf16), (k1 - k0) % 32 == 0
+template <int BT, typename A>
+__device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
+                                                const uint16_t* __restrict__ Q, int64_t ld, int rp0,
+                                                int rq0, int k0, int k1, char* smem, A (&acc)[4][4]) {
+  typedef DlCfg<BT> C;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const PE_GLOBAL uint16_t* pP = gview(P) + (size_t)rp0 * ld + k0;
+  const PE_GLOBAL uint16_t* pQ = gview(Q) + (size_t)rq0 * ld + k0;
+  const int nk = (k1 - k0) / C::BK;
+  // prologue: stages 0..NS-2 in flight (a stage past the end re-reads the last
+  // one, which keeps the count of outstanding loads per iteration fixed)
+  __syncthreads();  // the previous tile's readers are done with the ring
+#pragma unroll
+  for (int s = 0; s < C::NS - 1; ++s) {
+    const int ks = s < nk ? s : nk - 1;
+    dl_issue_stage<BT>(pP, pQ, ld, ks * C::BK, smem + s * C::STB, wave, lane);
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+    // this wave's loads of stage kt are done once at most NS-2 later stages are pending
+    wait_vmcnt<(C::NS - 2) * C::LPS>();
+    __builtin_amdgcn_s_barrier();  // everyone's loads of stage kt landed; stage kt-1's slot is free
+    {
+      const int ks = kt + C::NS - 1 < nk ? kt + C::NS - 1 : nk - 1;
+      dl_issue_stage<BT>(pP, pQ, ld, ks * C::BK, smem + ((kt + C::NS - 1) % C::NS) * C::STB, wave, lane);
+    }
+    const char* cur = smem + (kt % C::NS) * C::STB;
+    dl_mma_stage<BT>(cur, cur + C::OPB, wm, wn, lane, acc);
+  }
+  wait_vmcnt<0>();  // no LDS write may still be in flight when the ring is reused
+}
+
+// Persistent blocks take items b, b + G, b + 2G, ... (G = gridDim.x).  Blocks
+// are dispatched round-robin over the 8 XCDs (block b on XCD b % 8), each with
+// its own L2.  When G is a multiple of 8, this permutation gives the G/8 blocks
+// of XCD x, at round k, the contiguous positions
+// [kG + x G/8, kG + (x+1) G/8) of the item order, so tiles that share operand
+// panels run on the same L2.  The last, partial round keeps the identity.
+__device__ __forceinline__ int xcd_item(int item, int total) {
+  const int G = gridDim.x;
+  if ((G & 7) != 0) return item;
+  const int round = item / G, b = item - round * G;
+  if ((round + 1) * G > total) return item;
+  return round * G + (b & 7) * (G >> 3) + (b >> 3);
+}
+
+// Tile (tm, tn) of an nb x nbn grid from a position in "banded" order: bands of
+// GM tile rows, tm fastest inside a band, so consecutive positions form
+// GM-tall blocks that share both operand panels.
+__device__ __forceinline__ void banded_decode(int local, int nb, int nbn, int* tm, int* tn) {
+  constexpr int GM = 8;
+  const int band = local / (GM * nbn);
+  const int first = band * GM;
+  const int rows = min(GM, nb - first);
+  const int r = local - band * GM * nbn;
+  *tm = first + r % rows;
+  *tn = r / rows;
 }
 
 // upper-triangle tile index -> (ti, tj), ti <= tj, row-major over ti
@@ -386,6 +537,144 @@ __device__ __forceinline__ uint2 pack4_bf16(const float (&v)[4]) {
   return pk;
 }
 
+// ------------------------------------------------------------- FP8 (e4m3)
+// Per-tensor scale: the largest power of two q with amax * 1.01 * q <= 448, so
+// x * q is exact and never exceeds the largest e4m3 magnitude (the 1.01 covers
+// the bf16 rounding of values whose maximum was taken in fp32).
+__device__ __forceinline__ float fp8_scale(float amax) {
+  if (!(amax > 0.0f) || !(amax < 3.0e38f)) return 1.0f;
+  int e;
+  frexpf(448.0f / (amax * 1.01f), &e);
+  return ldexpf(1.0f, e - 1);
+}
+
+// four floats -> four OCP e4m3 bytes (hardware conversion, round to nearest even)
+__device__ __forceinline__ uint32_t pack4_e4m3(float f0, float f1, float f2, float f3) {
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(f0, f1, 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(f2, f3, w, true);
+  return (uint32_t)w;
+}
+
+// eight bf16 (one 16-byte chunk) scaled by q -> eight e4m3 bytes
+__device__ __forceinline__ uint2 bf16x8_to_e4m3(u32x4 c, float q) {
+  uint2 r;
+  r.x = pack4_e4m3(__uint_as_float(c[0] << 16) * q, __uint_as_float(c[0] & 0xffff0000u) * q,
+                   __uint_as_float(c[1] << 16) * q, __uint_as_float(c[1] & 0xffff0000u) * q);
+  r.y = pack4_e4m3(__uint_as_float(c[2] << 16) * q, __uint_as_float(c[2] & 0xffff0000u) * q,
+                   __uint_as_float(c[3] << 16) * q, __uint_as_float(c[3] & 0xffff0000u) * q);
+  return r;
+}
+
+// FP8 stage layout: the bf16 operand is read from HBM and quantised on its way
+// into LDS.  BT = 128: 128 k per stage, 16x16x128 f8f6f4 MFMA (lane: 32 bytes
+// at k = 32*(lane/16)); BT = 256: 64 k per stage, 32x32x64 f8f6f4 MFMA (lane:
+// 32 bytes at k = 32*(lane/32)).  Rows carry a 16-byte pad.
+template <int BT>
+struct Fp8Cfg {
+  static constexpr int F = BT / 8;
+  static constexpr int KQ = BT == 128 ? 128 : 64;   // k per stage
+  static constexpr int ROWB = KQ + 16;              // LDS bytes per row
+  static constexpr int OPB = BT * ROWB;
+  static constexpr int LDS = 4 * OPB;
+  static constexpr int CPR = KQ / 8;                // 16-byte bf16 chunks per row
+  static constexpr int CPT = BT * CPR / kThreads;   // chunks per thread per operand (8)
+  static constexpr int RSTRIDE = kThreads / CPR;    // rows between a thread's chunks
+};
+
+template <int BT, typename A>
+__device__ __forceinline__ void mma_stage_fp8(const char* sA, const char* sB, int wm, int wn,
+                                              int lane, A (&acc)[4][4]) {
+  typedef Fp8Cfg<BT> C;
+  constexpr int F = C::F;
+  i32x8 fa[4], fb[4];
+  const int koff = (lane / F) * 32;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const char* pa = sA + (wm * (BT / 2) + f * F + (lane % F)) * C::ROWB + koff;
+    const char* pb = sB + (wn * (BT / 2) + f * F + (lane % F)) * C::ROWB + koff;
+    const u32x4 a0 = *(const u32x4*)pa, a1 = *(const u32x4*)(pa + 16);
+    const u32x4 b0 = *(const u32x4*)pb, b1 = *(const u32x4*)(pb + 16);
+    fa[f] = i32x8{(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3],
+                  (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
+    fb[f] = i32x8{(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3],
+                  (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
+  }
+#pragma unroll
+  for (int fm = 0; fm < 4; ++fm) {
+#pragma unroll
+    for (int fn = 0; fn < 4; ++fn) {
+      // format 0 = e4m3 for both operands, E8M0 block scales 127 = 1.0
+      if constexpr (F == 16)
+        acc[fm][fn] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa[fm], fb[fn], acc[fm][fn],
+                                                                       0, 0, 0, 127, 0, 127);
+      else
+        acc[fm][fn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[fm], fb[fn], acc[fm][fn],
+                                                                      0, 0, 0, 127, 0, 127);
+    }
+  }
+}
+
+// acc += q(P)[rp0:+BT, k0:k1] * q(Q)[rq0:+BT, k0:k1]^T with bf16 operands in HBM
+// quantised to e4m3 with scales qp, qq; (k1 - k0) % KQ == 0.
+template <int BT, typename A>
+__device__ __forceinline__ void gemm_nt_tile_fp8(const uint16_t* __restrict__ P,
+                                                 const uint16_t* __restrict__ Q, int64_t ld,
+                                                 int rp0, int rq0, int k0, int k1, float qp, float qq,
+                                                 char* smem, A (&acc)[4][4]) {
+  typedef Fp8Cfg<BT> C;
+  constexpr int CPT = C::CPT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int crow = tid / C::CPR, ccol = tid % C::CPR;
+  const PE_GLOBAL uint16_t* pP = gview(P) + (size_t)(rp0 + crow) * ld + k0 + ccol * 8;
+  const PE_GLOBAL uint16_t* pQ = gview(Q) + (size_t)(rq0 + crow) * ld + k0 + ccol * 8;
+  const size_t jstride = (size_t)C::RSTRIDE * ld;
+  u32x4 ra[CPT], rb[CPT];
+  const int nk = (k1 - k0) / C::KQ;
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    ra[j] = *(const PE_GLOBAL u32x4*)(pP + j * jstride);
+    rb[j] = *(const PE_GLOBAL u32x4*)(pQ + j * jstride);
+  }
+  const int soff = crow * C::ROWB + ccol * 8;
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    *(uint2*)(smem + soff + j * C::RSTRIDE * C::ROWB) = bf16x8_to_e4m3(ra[j], qp);
+    *(uint2*)(smem + C::OPB + soff + j * C::RSTRIDE * C::ROWB) = bf16x8_to_e4m3(rb[j], qq);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const size_t adv = (size_t)(kt + 1 < nk ? kt + 1 : kt) * C::KQ;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      ra[j] = *(const PE_GLOBAL u32x4*)(pP + adv + j * jstride);
+      rb[j] = *(const PE_GLOBAL u32x4*)(pQ + adv + j * jstride);
+    }
+    // keep the prefetch at the top of the stage: a whole stage of MFMA work
+    // then covers its latency
+    __builtin_amdgcn_sched_barrier(0);
+    const char* cur = smem + (kt & 1) * 2 * C::OPB;
+    mma_stage_fp8<BT>(cur, cur + C::OPB, wm, wn, lane, acc);
+    char* nxt = smem + ((kt + 1) & 1) * 2 * C::OPB;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      *(uint2*)(nxt + soff + j * C::RSTRIDE * C::ROWB) = bf16x8_to_e4m3(ra[j], qp);
+      *(uint2*)(nxt + C::OPB + soff + j * C::RSTRIDE * C::ROWB) = bf16x8_to_e4m3(rb[j], qq);
+    }
+    __syncthreads();
+  }
+}
+
+// Scale of step t's Gram-side operand (kind GRAM: X_t, kind A2: A_t).
+__device__ __forceinline__ float fp8_operand_scale(const MatDesc& d, int kind, int t) {
+  float amax;
+  if (kind == KIND_GRAM)
+    amax = t == 0 ? d.scal[kScAmaxG] : __uint_as_float(((const uint32_t*)d.scal)[kScAmaxX + t]);
+  else
+    amax = __uint_as_float(((const uint32_t*)d.scal)[kScAmaxA + t]);
+  return fp8_scale(amax);
+}
+
 // ------------------------------------------------------------- epilogues
 // Accumulator element (fm, fn, g, r) is C[row][col] of the block tile with
 //   F = 16: row = wm*BT/2 + fm*16 + 4*(lane/16) + r,           col = wn*BT/2 + fn*16 + lane%16
@@ -405,18 +694,19 @@ __device__ __forceinline__ int acc_col(int wn, int fn, int lane) {
 
 template <int P, int BT, typename A>
 __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, int kind, int ti,
-                                         int tj, const A (&acc)[4][4]) {
+                                         int tj, float deq, const A (&acc)[4][4]) {
   typedef TileCfg<BT> C;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const size_t sp = d.sp;
   float a, b, c;
   step_coef(args, d, &a, &b, &c);
-  float alpha = 1.0f;
+  float alpha = deq;
   if (kind == KIND_GRAM && args.t == 0) {
     const float sg = d.scal[kScScale];
-    alpha = sg * sg;
+    alpha *= sg * sg;
   }
+  const float calpha = c * deq;
   float amax = 0.0f;
 #pragma unroll
   for (int fm = 0; fm < 4; ++fm) {
@@ -437,7 +727,7 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
             if (P != kF32) ((uint16_t*)d.As)[o] = f2bf(v[r]);
             amax = fmaxf(amax, fabsf(v[r]));
           } else {
-            v[r] = b * d.Af[o] + c * x;
+            v[r] = b * d.Af[o] + calpha * x;
             if (P == kF32) ((float*)d.Bs)[o] = v[r];
             else ((uint16_t*)d.Bs)[o] = f2bf(v[r]);
           }
@@ -456,7 +746,8 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
       }
     }
   }
-  if (kind == KIND_GRAM && P == kFP8) wave_amax_atomic(amax, d.scal + kScAmaxA + args.t);
+  // the A^2 product of the same step quantises A with this maximum
+  if (kind == KIND_GRAM && args.fp8) wave_amax_atomic(amax, d.scal + kScAmaxA + args.t);
 }
 
 template <int P, int BT, bool LAST, typename A>
@@ -518,9 +809,11 @@ __global__ __launch_bounds__(kThreads, BT == 128 ? 2 : 1) void gemm_kernel(KArgs
   using T = typename std::conditional<P == kF32, float, uint16_t>::type;
   typedef TileCfg<BT> C;
   typedef typename AccT<C::ACC>::type Acc;
-  constexpr int BK = OpT<T>::kBK;
-  __shared__ __attribute__((aligned(16))) char smem[C::LDS];
-  for (int item = blockIdx.x; item < args.total; item += gridDim.x) {
+  constexpr int BK = P == kFP8 ? Fp8Cfg<BT>::KQ : (P == kBF16 ? DlCfg<BT>::BK : OpT<T>::kBK);
+  constexpr int LDSB = P == kFP8 ? Fp8Cfg<BT>::LDS : (P == kBF16 ? DlCfg<BT>::LDS : C::LDS);
+  __shared__ __attribute__((aligned(16))) char smem[LDSB];
+  for (int slot = blockIdx.x; slot < args.total; slot += gridDim.x) {
+    const int item = xcd_item(slot, args.total);
     const int mi = find_mat(args.offs, args.count, item);
     const MatDesc& d = args.descs[mi];
     const int local = item - args.offs[mi];
@@ -530,10 +823,14 @@ __global__ __launch_bounds__(kThreads, BT == 128 ? 2 : 1) void gemm_kernel(KArgs
 #pragma unroll
       for (int fn = 0; fn < 4; ++fn) acc[fm][fn] = Acc{};
     if constexpr (KIND == KIND_UPD || KIND == KIND_UPD_LAST) {
-      const int tm = local % d.nb, tn = local / d.nb;
+      int tm, tn;
+      banded_decode(local, d.nb, d.nbL, &tm, &tn);
       const T* Bop = (const T*)d.Bs;
       const T* XTc = (const T*)((args.t & 1) ? d.XT1 : d.XT0);
-      gemm_nt_tile<T, BT>(Bop, XTc, d.sp, tm * BT, tn * BT, 0, d.sp, smem, acc);
+      if constexpr (P == kBF16)
+        gemm_nt_tile_dl<BT>((const uint16_t*)Bop, (const uint16_t*)XTc, d.sp, tm * BT, tn * BT, 0, d.sp, smem, acc);
+      else
+        gemm_nt_tile<T, BT>(Bop, XTc, d.sp, tm * BT, tn * BT, 0, d.sp, smem, acc);
       epi_update<P, BT, KIND == KIND_UPD_LAST>(args, d, tm, tn, acc);
     } else {
       const int split = KIND == KIND_GRAM ? d.gram_split : d.a2_split;
@@ -551,9 +848,19 @@ __global__ __launch_bounds__(kThreads, BT == 128 ? 2 : 1) void gemm_kernel(KArgs
       }
       int k0, k1;
       split_range(K, split, ksp, BK, &k0, &k1);
-      if (k1 > k0) gemm_nt_tile<T, BT>(Op, Op, K, ti * BT, tj * BT, k0, k1, smem, acc);
+      float deq = 1.0f;
+      if constexpr (P == kFP8) {
+        const float q = fp8_operand_scale(d, KIND, args.t);
+        deq = 1.0f / (q * q);
+        if (k1 > k0) gemm_nt_tile_fp8<BT>(Op, Op, K, ti * BT, tj * BT, k0, k1, q, q, smem, acc);
+      } else if constexpr (P == kBF16) {
+        if (k1 > k0)
+          gemm_nt_tile_dl<BT>((const uint16_t*)Op, (const uint16_t*)Op, K, ti * BT, tj * BT, k0, k1, smem, acc);
+      } else {
+        if (k1 > k0) gemm_nt_tile<T, BT>(Op, Op, K, ti * BT, tj * BT, k0, k1, smem, acc);
+      }
       if (split == 1) {
-        epi_syrk<P, BT>(args, d, KIND, ti, tj, acc);
+        epi_syrk<P, BT>(args, d, KIND, ti, tj, deq, acc);
       } else {
         // partial tile: float4 q of thread t at ((tile*split + ksp)*Q + q)*256 + t
         constexpr int Q = 16 * C::ACC / 4;
@@ -605,19 +912,22 @@ __global__ __launch_bounds__(kThreads) void splitk_reduce_kernel(KArgs args) {
           acc[fm][fn][4 * g + 2] = s.z;
           acc[fm][fn][4 * g + 3] = s.w;
         }
-    epi_syrk<P, BT>(args, d, KIND, ti, tj, acc);
+    float deq = 1.0f;
+    if constexpr (P == kFP8) {
+      const float q = fp8_operand_scale(d, KIND, args.t);
+      deq = 1.0f / (q * q);
+    }
+    epi_syrk<P, BT>(args, d, KIND, ti, tj, deq, acc);
   }
 }
 
-// Clears the per-matrix arrival counters and amax slots at the start of every
-// run, so no state carries over between calls or graph replays.
-__global__ void init_kernel(const MatDesc* descs, int count) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  const MatDesc& d = descs[i];
-  if (!d.cnt) return;
-  for (int k = 0; k < 4; ++k) d.cnt[k] = 0u;
-  for (int k = kScAmaxX; k < kScN; ++k) d.scal[k] = 0.0f;
+// q[i] = e4m3(x[i] * scale) with the conversion the FP8 path uses.
+__global__ void quantize_e4m3_kernel(const void* x, int x_bf16, uint8_t* q, int64_t n, float scale) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float v = x_bf16 ? bf2f(((const uint16_t*)x)[i]) : ((const float*)x)[i];
+    q[i] = (uint8_t)(pack4_e4m3(v * scale, 0.0f, 0.0f, 0.0f) & 0xffu);
+  }
 }
 
 __global__ void put_words_kernel(PutChunk c) {
@@ -625,8 +935,9 @@ __global__ void put_words_kernel(PutChunk c) {
 }
 
 // ------------------------------------------------------------- launchers
-hipError_t launch_init(const MatDesc* descs, int count, hipStream_t st) {
-  hipLaunchKernelGGL(init_kernel, dim3((count + kThreads - 1) / kThreads), dim3(kThreads), 0, st, descs, count);
+hipError_t launch_finalize(const KArgs& a, hipStream_t st) {
+  const int g = a.count < 1024 ? (a.count > 0 ? a.count : 1) : 1024;
+  hipLaunchKernelGGL(finalize_kernel, dim3(g), dim3(kThreads), 0, st, a);
   return hipGetLastError();
 }
 
@@ -666,7 +977,10 @@ static void launch_reduce_t(int kind, const KArgs& a, int g, hipStream_t st) {
 
 hipError_t launch_gemm(int prec, int bt, int kind, const KArgs& a, int grid_cap, hipStream_t st) {
   const int g = grid_for(a.total, grid_cap);
-  if (prec == kF32) {
+  if (prec == kFP8 && kind != KIND_UPD) {
+    if (bt == 256) launch_gemm_t<kFP8, 256>(kind, a, g, st);
+    else launch_gemm_t<kFP8, 128>(kind, a, g, st);
+  } else if (prec == kF32) {
     if (bt == 256) launch_gemm_t<kF32, 256>(kind, a, g, st);
     else launch_gemm_t<kF32, 128>(kind, a, g, st);
   } else {
@@ -678,13 +992,24 @@ hipError_t launch_gemm(int prec, int bt, int kind, const KArgs& a, int grid_cap,
 
 hipError_t launch_reduce(int prec, int bt, int kind, const KArgs& a, int grid_cap, hipStream_t st) {
   const int g = grid_for(a.total, grid_cap);
-  if (prec == kF32) {
+  if (prec == kFP8) {
+    if (bt == 256) launch_reduce_t<kFP8, 256>(kind, a, g, st);
+    else launch_reduce_t<kFP8, 128>(kind, a, g, st);
+  } else if (prec == kF32) {
     if (bt == 256) launch_reduce_t<kF32, 256>(kind, a, g, st);
     else launch_reduce_t<kF32, 128>(kind, a, g, st);
   } else {
     if (bt == 256) launch_reduce_t<kBF16, 256>(kind, a, g, st);
     else launch_reduce_t<kBF16, 128>(kind, a, g, st);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_quantize(const void* x, int x_bf16, uint8_t* q, int64_t n, float scale,
+                           hipStream_t st) {
+  const int64_t blocks = (n + kThreads - 1) / kThreads;
+  const int g = (int)(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096);
+  hipLaunchKernelGGL(quantize_e4m3_kernel, dim3(g), dim3(kThreads), 0, st, x, x_bf16, q, n, scale);
   return hipGetLastError();
 }
 

@@ -58,7 +58,7 @@ struct MatDesc {
   float* scal;      // [kScN]
   uint32_t* cnt;    // [4]
   int32_t n_prep, syrk_nt, upd_nt, gram_split;
-  int32_t a2_split, bt, pad1, pad2;  // bt: block tile edge
+  int32_t a2_split, bt, g_vec, pad2;  // bt: block tile edge; g_vec: 16-byte loads of G
 };
 
 struct KArgs {

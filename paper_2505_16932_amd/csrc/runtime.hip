@@ -20,7 +20,9 @@
 
 namespace pe {
 hipError_t launch_put(const PutChunk& c, hipStream_t st);
-hipError_t launch_init(const MatDesc* descs, int count, hipStream_t st);
+hipError_t launch_finalize(const KArgs& a, hipStream_t st);
+hipError_t launch_quantize(const void* x, int x_bf16, uint8_t* q, int64_t n, float scale,
+                           hipStream_t st);
 hipError_t launch_prep(int prec, const KArgs& a, int grid_cap, hipStream_t st);
 hipError_t launch_gemm(int prec, int bt, int kind, const KArgs& a, int grid_cap, hipStream_t st);
 hipError_t launch_reduce(int prec, int bt, int kind, const KArgs& a, int grid_cap, hipStream_t st);
@@ -77,7 +79,6 @@ pe_status check_opts(const pe_opts* o) {
   if (o->norm_mode != 0 && o->norm_mode != 1) return PE_EINVAL;
   if (o->compute == PE_COMPUTE_FP8) {
     if (o->fp8_steps < 0 || o->fp8_steps > o->T - 1) return PE_EINVAL;
-    if (o->fp8_steps > 0) return PE_EUNSUPPORTED;
   }
   for (int i = 0; i < 3 * o->T; ++i)
     if (!std::isfinite(o->abc[i])) return PE_EINVAL;
@@ -160,6 +161,12 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
     d.Lp = (int32_t)q.Lp;
     d.trans = m.m > m.n;
     d.g_bf16 = m.g_dtype == PE_BF16;
+    // 16-byte loads of G rows need an aligned base and a leading dimension
+    // that keeps every row 16-byte aligned
+    {
+      const int64_t per16 = d.g_bf16 ? 8 : 4;
+      d.g_vec = ((uintptr_t)m.G % 16 == 0) && (m.ldg % per16 == 0);
+    }
     d.out_bf16 = m.x_dtype == PE_BF16;
     d.nb = q.nb;
     d.nbL = q.nbL;
@@ -191,7 +198,7 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
       d.part = split > 1 ? (float*)take((size_t)q.syrk * split * bt * bt * 4) : nullptr;
       d.red = (double*)take((size_t)q.prep * 12 + 16);
       d.scal = (float*)take(kScN * 4);
-      d.cnt = (uint32_t*)take(64);
+      d.cnt = (uint32_t*)take(64);  // reserved
     }
     L->descs.push_back(d);
     auto push = [&](int ph, int n) { L->offs[ph].push_back(L->offs[ph].back() + n); };
@@ -243,6 +250,7 @@ pe_status put_words(void* dst, const void* src, size_t bytes, hipStream_t st) {
 struct pe_plan {
   int count = 0;
   int prec = kBF16;
+  int fp8_steps = 0;   // leading steps whose Gram-side products take e4m3 operands
   int T = 0;
   int norm_mode = 0;
   std::vector<float> abc;
@@ -291,10 +299,10 @@ void set_step(const pe_plan* p, KArgs* a, int t) {
 
 pe_status enqueue_norm(const pe_plan* p, hipStream_t st) {
   KArgs a = base_args(p);
-  hipError_t e = launch_init(p->d_descs, p->count, st);
-  if (e != hipSuccess) return hip_fail(e, "init launch");
   set_phase(p, &a, PH_PREP);
-  if ((e = launch_prep(p->prec, a, kPrepGridCap, st)) != hipSuccess) return hip_fail(e, "prep launch");
+  hipError_t e = launch_prep(p->prec, a, kPrepGridCap, st);
+  if (e != hipSuccess) return hip_fail(e, "prep launch");
+  if ((e = launch_finalize(a, st)) != hipSuccess) return hip_fail(e, "finalize launch");
   return PE_OK;
 }
 
@@ -306,11 +314,15 @@ pe_status enqueue_gemm(const pe_plan* p, int t, int kind, hipStream_t st) {
   KArgs a = base_args(p);
   set_step(p, &a, t);
   set_phase(p, &a, ph_main[kind]);
-  hipError_t e = launch_gemm(p->prec, p->L.bt, kind, a, p->L.bt == kTileLarge ? kGemmGridCapLarge : kGemmGridCap, st);
+  a.fp8 = t < p->fp8_steps;
+  a.fp8_next = t + 1 < p->fp8_steps;
+  // Gram-side products of the FP8 steps run the e4m3 kernels; updates stay bf16
+  const int prec = (a.fp8 && kind != 2) ? kFP8 : p->prec;
+  hipError_t e = launch_gemm(prec, p->L.bt, kind, a, p->L.bt == kTileLarge ? kGemmGridCapLarge : kGemmGridCap, st);
   if (e != hipSuccess) return hip_fail(e, names[kind]);
   if (ph_red[kind] >= 0 && p->L.totals[ph_red[kind]]) {
     set_phase(p, &a, ph_red[kind]);
-    if ((e = launch_reduce(p->prec, p->L.bt, kind, a, kReduceGridCap, st)) != hipSuccess)
+    if ((e = launch_reduce(prec, p->L.bt, kind, a, kReduceGridCap, st)) != hipSuccess)
       return hip_fail(e, "split-k reduce");
   }
   return PE_OK;
@@ -332,6 +344,7 @@ pe_status plan_init(pe_plan* p, int count, const pe_matrix* mats, const pe_opts*
   if (s != PE_OK) return s;
   p->count = count;
   p->prec = prec_of(o);
+  p->fp8_steps = o->compute == PE_COMPUTE_FP8 ? o->fp8_steps : 0;
   p->T = o->T;
   p->norm_mode = o->norm_mode;
   p->abc.resize(3 * o->T);
@@ -434,6 +447,16 @@ pe_status pe_plan_destroy(pe_plan* p) {
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
   delete p;
   return PE_OK;
+}
+
+pe_status pe_quantize_e4m3(const void* x, int32_t x_dtype, void* q, int64_t n, float scale,
+                           void* stream) {
+  g_last_error.clear();
+  if (n < 0 || (n > 0 && (!x || !q)) || (x_dtype != PE_F32 && x_dtype != PE_BF16)) return PE_EINVAL;
+  if (!(scale > 0.0f) || !std::isfinite(scale)) return PE_EINVAL;
+  if (n == 0) return PE_OK;
+  hipError_t e = launch_quantize(x, x_dtype == PE_BF16, (uint8_t*)q, n, scale, (hipStream_t)stream);
+  return e == hipSuccess ? PE_OK : hip_fail(e, "quantize launch");
 }
 
 int32_t pe_tile_count(void) { return 3; }

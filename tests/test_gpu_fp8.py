@@ -1,0 +1,119 @@
+"""The FP8 (e4m3) variant: the device quantiser bit for bit against the
+oracle's round-to-nearest-even e4m3 codes, and the iteration with e4m3
+Gram-side products in its first steps against the FP64 oracle (bar 3e-2)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import lowprec as LP
+from tests.gpu_util import device_input, oracle_same_iteration, oracle_schedule, relf, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pe():
+    import paper_2505_16932_amd as pe
+    pe.lib()
+    return pe
+
+
+def _grid_values():
+    """Every e4m3 magnitude, the midpoints between neighbours (ties), points a
+    quarter of the way in both directions, and random values, up to 448."""
+    vals = []
+    for c in range(0x7F):                                  # 0x7F is NaN
+        e, m = (c >> 3) & 0xF, c & 7
+        vals.append((m / 8.0) * 2.0 ** -6 if e == 0 else (1 + m / 8.0) * 2.0 ** (e - 7))
+    vals = np.array(vals)
+    mids = 0.5 * (vals[1:] + vals[:-1])
+    q1 = vals[:-1] + 0.25 * (vals[1:] - vals[:-1])
+    q3 = vals[:-1] + 0.75 * (vals[1:] - vals[:-1])
+    r = synth.rng(4242)
+    rnd = r.uniform(0, 448, 4000)
+    small = r.uniform(0, 2.0 ** -5, 2000)
+    allv = np.concatenate([vals, mids, q1, q3, rnd, small])
+    return np.concatenate([allv, -allv])
+
+
+@pytest.mark.parametrize("scale", [1.0, 2.0 ** 7, 2.0 ** -3])
+def test_quantizer_bit_exact(pe, scale):
+    import torch
+    v = _grid_values() / scale
+    x = torch.from_numpy(v.astype(np.float32)).cuda()
+    q = pe.quantize_e4m3(x, scale)
+    torch.cuda.synchronize()
+    got = q.cpu().numpy()
+    ref = LP.e4m3_code(v.astype(np.float32).astype(np.float64) * scale)
+    bad = np.flatnonzero(got != ref)
+    assert bad.size == 0, [(v[i] * scale, got[i], ref[i]) for i in bad[:10]]
+
+
+def test_quantizer_bf16_input(pe):
+    import torch
+    v = synth.rng(4243).standard_normal(5000) * 0.01
+    x = torch.from_numpy(v.astype(np.float32)).to(torch.bfloat16).cuda()
+    scale = 2.0 ** 12
+    q = pe.quantize_e4m3(x, scale)
+    torch.cuda.synchronize()
+    vals = x.double().cpu().numpy()
+    assert np.array_equal(q.cpu().numpy(), LP.e4m3_code(vals * scale))
+
+
+FP8_CASES = [((768, 2304), 2, 3), ((768, 2304), 2, 1), ((3072, 768), 2, 3), ((3072, 768), 2, 2),
+             ((384, 1000), 1, 3), ((384, 1000), 1, 1), ((130, 260), 1, 2), ((130, 260), 1, 1)]
+
+
+@pytest.mark.parametrize("shape,tile,fp8_steps", FP8_CASES)
+def test_fp8_gram_steps_parity(pe, fp8_steps, shape, tile):
+    """sigma_i = 1/i with Haar vectors (the batch workloads' spectrum).  With
+    s = 130 the normalised spectrum starts at 6e-3 and most values are pushed
+    through the non-monotone steps early, where three e4m3 steps exceed the bar
+    (3.6e-2 measured); two steps stay within it."""
+    import torch
+    G64 = synth.powerlaw(1003 + shape[0] % 97, shape[0], shape[1]).G
+    G, vals = device_input(G64, torch.bfloat16)
+    abc = oracle_schedule(5)
+    X = pe.polar(G, T=5, abc=abc, compute="fp8", fp8_steps=fp8_steps, out_dtype=torch.float32,
+                 tile=tile)
+    Y = pe.polar(G, T=5, abc=abc, compute="bf16", out_dtype=torch.float32, tile=tile)
+    torch.cuda.synchronize()
+    ref = oracle_same_iteration(vals, abc)
+    e8, e16 = relf(to_np(X), ref), relf(to_np(Y), ref)
+    print(f"[fp8] {shape} steps={fp8_steps} relF fp8={e8:.3e} bf16={e16:.3e}", flush=True)
+    assert e8 <= 3e-2
+    assert e8 > e16 * 0.5   # the e4m3 products really ran (coarser than bf16)
+
+
+def test_fp8_loguniform_first_step(pe):
+    """4096 x 1024, log-uniform spectrum: e4m3 in the first step only."""
+    import torch
+    S = synth.loguniform(1002)
+    G, vals = device_input(S.G, torch.bfloat16)
+    abc = oracle_schedule(6)
+    X = pe.polar(G, T=6, abc=abc, compute="fp8", fp8_steps=1, out_dtype=torch.float32)
+    torch.cuda.synchronize()
+    err = relf(to_np(X), oracle_same_iteration(vals, abc))
+    print(f"[fp8] 4096x1024 loguniform T=6 fp8_steps=1 relF={err:.3e}", flush=True)
+    assert err <= 3e-2
+
+
+def test_fp8_batched_and_graph(pe):
+    import torch
+    shapes = [(768, 2304), (768, 768), (3072, 768)]
+    Gs, vals = [], []
+    for k, s in enumerate(shapes):
+        g, v = device_input(synth.powerlaw(1100 + k, *s).G, torch.bfloat16)
+        Gs.append(g)
+        vals.append(v)
+    abc = oracle_schedule(5)
+    plan = pe.Plan(Gs, T=5, abc=abc, compute="fp8", fp8_steps=3, out_dtype=torch.float32)
+    eager = [x.clone() for x in plan.launch(graph=False)]
+    for _ in range(3):
+        plan.launch(graph=True)
+        torch.cuda.synchronize()
+        for a, b in zip(plan.outs, eager):
+            assert torch.equal(a, b)
+    for X, v in zip(plan.outs, vals):
+        assert relf(to_np(X), oracle_same_iteration(v, abc)) <= 3e-2
+    plan.close()
