@@ -111,7 +111,24 @@ typedef struct {
                           1: X_0 = G/(||G||_F + 1e-2) (Algorithm 1) */
   int32_t tile;        /* 0 = library choice (autotuned table if loaded), else a
                           tile id from pe_tile_count()/pe_tile_name() */
+  /* Learned choice of l (optional).  With `predictor` (device pointer to
+   * PE_MLP_PARAMS floats, see pe_mlp_*) or force_class >= 0, each matrix runs
+   * one of PE_CLASSES schedules, l = 1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4,
+   * 3e-5 (class 4 uses `abc`, the others pe_coeffs(l, T) with default options),
+   * chosen on the device from tr(A^k), k = 1..4, of the step-1 Gram matrix.
+   * Afterwards ||X X^T - I||_2 is estimated by power iteration; matrices above
+   * fallback_tau (> 0) that did not run class 4 are recomputed from G with it. */
+  const float* predictor;  /* device, PE_MLP_PARAMS floats, or NULL */
+  int32_t force_class;     /* -1: the network's choice; 0..7: this class (tests) */
+  float fallback_tau;      /* <= 0: no estimate and no fallback */
 } pe_opts;
+
+#define PE_CLASSES 8
+#define PE_FIXED_CLASS 4
+#define PE_FEATURES 16
+/* MLP 16 -> 64 -> 64 -> 8, ReLU, softmax cross-entropy.  Flat FP32 layout:
+ * W1 [16 x 64] (row = input), b1 [64], W2 [64 x 64], b2 [64], W3 [64 x 8], b3 [8]. */
+#define PE_MLP_PARAMS 5768
 
 /* Bytes of device workspace needed by pe_polar / pe_polar_batched / a plan
  * for these matrices and options (0 on invalid input).  Workspace must be
@@ -159,12 +176,43 @@ pe_status pe_plan_launch_phase(pe_plan* plan, int32_t step, int32_t phase, void*
 pe_status pe_quantize_e4m3(const void* x, int32_t x_dtype, void* q, int64_t n, float scale,
                            void* stream);
 
-/* Tile configurations compiled into the library and the autotuned table.
- * pe_tile_table_load reads a text table "<shape-class> <tile-id>" per line
- * (written by the autotuner); it replaces the built-in choices. */
+/* After a learned call (plan launched and synchronised): per matrix the class
+ * used, the 16 features, the ||X X^T - I||_2 estimate and the fallback flag
+ * (host outputs, each nullable; classes/flags count ints, feats count*16 and
+ * est count floats).  Synchronous copy from the plan's workspace. */
+pe_status pe_plan_selection(pe_plan* plan, int32_t* classes, float* feats, float* est,
+                            int32_t* flags);
+
+/* ---------------------------------------------------------------------------
+ * Training kernels of the l-predictor (device pointers, FP32, asynchronous).
+ * feats: B x 16 row-major; labels: B class indices.  Workspace for B samples:
+ * pe_mlp_workspace_size(B) bytes (256-byte aligned).
+ * ------------------------------------------------------------------------- */
+size_t pe_mlp_workspace_size(int32_t B);
+/* logits: B x 8 */
+pe_status pe_mlp_forward(const float* params, const float* feats, int32_t B, float* logits,
+                         void* stream);
+/* grad: PE_MLP_PARAMS, mean cross-entropy gradient; loss: 1 float (nullable) */
+pe_status pe_mlp_grad(const float* params, const float* feats, const int32_t* labels, int32_t B,
+                      float* grad, float* loss, void* ws, size_t ws_bytes, void* stream);
+/* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; step >= 1) in
+ * place on params with moment buffers m, v (PE_MLP_PARAMS each, zero at step 1) */
+pe_status pe_mlp_train_step(float* params, float* m, float* v, int32_t step, float lr,
+                            const float* feats, const int32_t* labels, int32_t B, float* loss,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* Tile configurations compiled into the library (0 = auto, 1 = 128 x 128,
+ * 2 = 256 x 256) and the autotuned table (written by
+ * paper_2505_16932_amd/autotune.py); loading a table replaces the previous one. */
 int32_t pe_tile_count(void);
 const char* pe_tile_name(int32_t tile_id);
+/* Lines "<shape-class> <tile-id>" ('#' starts a comment); tile-id 1 or 2.
+ * With a table loaded and opts.tile = 0, each matrix of a call votes for its
+ * class's tile with its flop count (3 s^2 L + s^3); calls with a matrix whose
+ * class is missing keep the built-in choice.  PE_EINVAL on a malformed file. */
 pe_status pe_tile_table_load(const char* path);
+/* Shape class of an m x n matrix for the compute mode (the table's key). */
+const char* pe_shape_class(int32_t compute, int64_t m, int64_t n);
 
 const char* pe_status_string(pe_status st);
 /* Text of the last HIP error seen by this thread (empty if none). */

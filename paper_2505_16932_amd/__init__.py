@@ -56,7 +56,15 @@ class Matrix(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("T", ctypes.c_int32), ("abc", ctypes.POINTER(ctypes.c_double)),
                 ("compute", ctypes.c_int32), ("fp8_steps", ctypes.c_int32),
-                ("norm_mode", ctypes.c_int32), ("tile", ctypes.c_int32)]
+                ("norm_mode", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("predictor", ctypes.c_void_p), ("force_class", ctypes.c_int32),
+                ("fallback_tau", ctypes.c_float)]
+
+
+MLP_PARAMS = 5768
+CLASSES = 8
+FIXED_CLASS = 4
+FEATURES = 16
 
 
 _LIB = None
@@ -102,6 +110,23 @@ def lib() -> ctypes.CDLL:
         L.pe_quantize_e4m3.restype = ctypes.c_int
         L.pe_quantize_e4m3.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                        ctypes.c_int64, ctypes.c_float, ctypes.c_void_p]
+        L.pe_plan_selection.restype = ctypes.c_int
+        L.pe_plan_selection.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p]
+        L.pe_mlp_workspace_size.restype = ctypes.c_size_t
+        L.pe_mlp_workspace_size.argtypes = [ctypes.c_int32]
+        L.pe_mlp_forward.restype = ctypes.c_int
+        L.pe_mlp_forward.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.c_void_p, ctypes.c_void_p]
+        L.pe_mlp_grad.restype = ctypes.c_int
+        L.pe_mlp_grad.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                  ctypes.c_void_p]
+        L.pe_mlp_train_step.restype = ctypes.c_int
+        L.pe_mlp_train_step.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_int32, ctypes.c_float, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.pe_tile_count.restype = ctypes.c_int32
         L.pe_tile_name.restype = ctypes.c_char_p
         L.pe_tile_name.argtypes = [ctypes.c_int32]
@@ -110,6 +135,11 @@ def lib() -> ctypes.CDLL:
         L.pe_status_string.restype = ctypes.c_char_p
         L.pe_status_string.argtypes = [ctypes.c_int]
         L.pe_last_error.restype = ctypes.c_char_p
+        L.pe_shape_class.restype = ctypes.c_char_p
+        L.pe_shape_class.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64]
+        table = os.path.join(HERE, "tile_table.txt")
+        if os.path.exists(table) and os.environ.get("PE_TILE_TABLE", "1") != "0":
+            _check(L.pe_tile_table_load(table.encode()), "pe_tile_table_load")
         _LIB = L
     return _LIB
 
@@ -174,13 +204,24 @@ def _matrix(G, X) -> Matrix:
                   _dtype_code(G.dtype), _dtype_code(X.dtype))
 
 
-def _opts(T, abc, compute, fp8_steps, norm_mode, tile):
+def _opts(T, abc, compute, fp8_steps, norm_mode, tile, predictor=None, force_class=-1,
+          fallback_tau=0.0):
     abc = np.ascontiguousarray(np.asarray(abc, dtype=np.float64).reshape(-1))
     if abc.size != 3 * T:
         raise ValueError("abc must hold 3*T coefficients")
+    pred = 0
+    if predictor is not None:
+        if predictor.numel() != MLP_PARAMS or not predictor.is_cuda or predictor.dtype != _torch().float32:
+            raise ValueError("predictor must be a float32 device tensor of MLP_PARAMS values")
+        pred = predictor.data_ptr()
     o = Opts(int(T), abc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), COMPUTE[compute],
-             int(fp8_steps), int(norm_mode), int(tile))
+             int(fp8_steps), int(norm_mode), int(tile), pred, int(force_class), float(fallback_tau))
     return o, abc
+
+
+def _torch():
+    import torch
+    return torch
 
 
 def _schedule(T, ell, abc):
@@ -212,23 +253,84 @@ def workspace_size(shapes, T=5, compute="bf16", fp8_steps=0) -> int:
     return int(lib().pe_workspace_size(len(shapes), mats, ctypes.byref(o)))
 
 
+# ------------------------------------------------------------ l-predictor
+def mlp_forward(params, feats, stream=None):
+    """logits (B x 8) of the predictor MLP (device kernels)."""
+    torch = _torch()
+    B = feats.shape[0]
+    logits = torch.empty((B, CLASSES), dtype=torch.float32, device=feats.device)
+    _check(lib().pe_mlp_forward(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(feats.data_ptr()),
+                                B, ctypes.c_void_p(logits.data_ptr()), _stream(stream)),
+           "pe_mlp_forward")
+    return logits
+
+
+def _mlp_ws(B, device):
+    n = int(lib().pe_mlp_workspace_size(B))
+    return _workspace(n, device) + (n,)
+
+
+def mlp_grad(params, feats, labels, stream=None):
+    """(mean cross-entropy, gradient) on the device."""
+    torch = _torch()
+    B = feats.shape[0]
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=feats.device)
+    loss = torch.empty(1, dtype=torch.float32, device=feats.device)
+    buf, ws, n = _mlp_ws(B, feats.device)
+    _check(lib().pe_mlp_grad(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(feats.data_ptr()),
+                             ctypes.c_void_p(labels.data_ptr()), B, ctypes.c_void_p(grad.data_ptr()),
+                             ctypes.c_void_p(loss.data_ptr()), ctypes.c_void_p(ws), n, _stream(stream)),
+           "pe_mlp_grad")
+    return loss, grad
+
+
+class MLPTrainer:
+    """Adam on the device: params, moments and the per-step workspace stay resident."""
+
+    def __init__(self, params, B):
+        torch = _torch()
+        self.params = params
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.step = 0
+        self.B = B
+        self.loss = torch.empty(1, dtype=torch.float32, device=params.device)
+        self._buf, self._ws, self._n = _mlp_ws(B, params.device)
+
+    def train_step(self, feats, labels, lr, stream=None):
+        assert feats.shape[0] == self.B
+        self.step += 1
+        _check(lib().pe_mlp_train_step(ctypes.c_void_p(self.params.data_ptr()),
+                                       ctypes.c_void_p(self.m.data_ptr()),
+                                       ctypes.c_void_p(self.v.data_ptr()), self.step, float(lr),
+                                       ctypes.c_void_p(feats.data_ptr()),
+                                       ctypes.c_void_p(labels.data_ptr()), self.B,
+                                       ctypes.c_void_p(self.loss.data_ptr()), ctypes.c_void_p(self._ws),
+                                       self._n, _stream(stream)), "pe_mlp_train_step")
+        return self.loss
+
+
 def polar(G, T: int = 5, ell: float = 1e-3, abc=None, compute: str = "bf16", out=None,
-          out_dtype=None, fp8_steps: int = 0, norm_mode: int = 0, tile: int = 0, stream=None):
+          out_dtype=None, fp8_steps: int = 0, norm_mode: int = 0, tile: int = 0, stream=None,
+          predictor=None, force_class: int = -1, fallback_tau: float = 0.0):
     """X_T for one matrix (pe_polar).  Returns a new tensor unless ``out`` is given."""
     return polar_batched([G], T, ell, abc, compute, [out] if out is not None else None,
-                         out_dtype, fp8_steps, norm_mode, tile, stream, _single=True)[0]
+                         out_dtype, fp8_steps, norm_mode, tile, stream, predictor, force_class,
+                         fallback_tau, _single=True)[0]
 
 
 def polar_batched(Gs, T: int = 5, ell: float = 1e-3, abc=None, compute: str = "bf16", outs=None,
                   out_dtype=None, fp8_steps: int = 0, norm_mode: int = 0, tile: int = 0,
-                  stream=None, _single: bool = False):
+                  stream=None, predictor=None, force_class: int = -1, fallback_tau: float = 0.0,
+                  _single: bool = False):
     """X_T for a list of matrices of any shapes (pe_polar_batched)."""
     import torch
     Gs = list(Gs)
     if outs is None:
         outs = [torch.empty(G.shape, dtype=out_dtype or G.dtype, device=G.device) for G in Gs]
     sched = _schedule(T, ell, abc)
-    o, _keep = _opts(T, sched, compute, fp8_steps, norm_mode, tile)
+    o, _keep = _opts(T, sched, compute, fp8_steps, norm_mode, tile, predictor, force_class,
+                     fallback_tau)
     mats = (Matrix * max(1, len(Gs)))()
     for i, (G, X) in enumerate(zip(Gs, outs)):
         mats[i] = _matrix(G, X)
@@ -267,14 +369,17 @@ class Plan:
     """Tile tables built once and the T-step sequence captured as a hipGraph."""
 
     def __init__(self, Gs, outs=None, T: int = 5, ell: float = 1e-3, abc=None, compute: str = "bf16",
-                 out_dtype=None, fp8_steps: int = 0, norm_mode: int = 0, tile: int = 0, stream=None):
+                 out_dtype=None, fp8_steps: int = 0, norm_mode: int = 0, tile: int = 0, stream=None,
+                 predictor=None, force_class: int = -1, fallback_tau: float = 0.0):
         import torch
         self.Gs = list(Gs)
         self.outs = outs if outs is not None else [
             torch.empty(G.shape, dtype=out_dtype or G.dtype, device=G.device) for G in self.Gs]
         self.T = T
         self.abc = _schedule(T, ell, abc)
-        o, self._abc_keep = _opts(T, self.abc, compute, fp8_steps, norm_mode, tile)
+        self._predictor = predictor
+        o, self._abc_keep = _opts(T, self.abc, compute, fp8_steps, norm_mode, tile, predictor,
+                                  force_class, fallback_tau)
         self._mats = (Matrix * max(1, len(self.Gs)))()
         for i, (G, X) in enumerate(zip(self.Gs, self.outs)):
             self._mats[i] = _matrix(G, X)
@@ -291,6 +396,17 @@ class Plan:
     def launch(self, graph: bool = True, stream=None):
         _check(lib().pe_plan_launch(self._h, _stream(stream), 1 if graph else 0), "pe_plan_launch")
         return self.outs
+
+    def selection(self):
+        """(classes, features, estimates, fallback flags) of a learned plan's last launch."""
+        n = len(self.Gs)
+        cls = np.zeros(n, dtype=np.int32)
+        flags = np.zeros(n, dtype=np.int32)
+        feats = np.zeros((n, FEATURES), dtype=np.float32)
+        est = np.zeros(n, dtype=np.float32)
+        _check(lib().pe_plan_selection(self._h, cls.ctypes.data, feats.ctypes.data, est.ctypes.data,
+                                       flags.ctypes.data), "pe_plan_selection")
+        return cls, feats, est, flags
 
     def launch_phase(self, step: int, phase: int, stream=None):
         """Diagnostic: one phase (0 norm, 1 Gram, 2 A^2+combine, 3 update) of one step."""

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libpe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["kernels.hip", "runtime.hip"]
+HIP_SOURCES = ["kernels.hip", "learned.hip", "runtime.hip"]
 CXX_SOURCES = ["coeffs.cpp"]
 
 # Packed-FP32 instructions are kept out of every device build.

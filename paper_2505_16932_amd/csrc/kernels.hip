@@ -69,10 +69,15 @@ __device__ __forceinline__ int find_mat(const int32_t* offs, int count, int item
 }
 
 
+// In the fallback re-run only the matrices whose estimate failed are recomputed.
+__device__ __forceinline__ bool skip_matrix(const KArgs& args, const MatDesc& d) {
+  return args.fallback && (d.flagp == nullptr || *d.flagp == 0);
+}
+
 __device__ __forceinline__ void step_coef(const KArgs& args, const MatDesc& d, float* a, float* b,
                                           float* c) {
   if (args.sel_coef) {
-    const float* p = args.sel_coef + ((size_t)d.sel * args.tmax + args.t) * 3;
+    const float* p = args.sel_coef + ((size_t)(*d.selp) * args.tmax + args.t) * 3;
     *a = p[0]; *b = p[1]; *c = p[2];
   } else {
     *a = args.a; *b = args.b; *c = args.c;
@@ -149,6 +154,7 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(KArgs args) {
   for (int item = blockIdx.x; item < args.total; item += gridDim.x) {
     const int mi = find_mat(args.offs, args.count, item);
     const MatDesc& d = args.descs[mi];
+    if (skip_matrix(args, d)) continue;
     const int local = item - args.offs[mi];
     const int ntk = d.Lp / kPrepTile;
     const int i0 = (local / ntk) * kPrepTile;   // rows of X (s side)
@@ -204,7 +210,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(KArgs args) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int mi = blockIdx.x; mi < args.count; mi += gridDim.x) {
     const MatDesc& d = args.descs[mi];
-    if (d.n_prep == 0) continue;
+    if (d.n_prep == 0 || skip_matrix(args, d)) continue;
     double acc = 0.0;
     float am = 0.0f;
     const float* rf = (const float*)(d.red + d.n_prep);
@@ -517,6 +523,11 @@ __device__ __forceinline__ void tri_decode(int u, int nb, int* ti, int* tj) {
   *tj = r + u;
 }
 
+// inverse of tri_decode
+__device__ __forceinline__ int tri_index(int ti, int tj, int nb) {
+  return ti * nb - (ti * (ti - 1)) / 2 + (tj - ti);
+}
+
 __device__ __forceinline__ void split_range(int K, int split, int ksp, int BK, int* k0, int* k1) {
   int per = (K + split - 1) / split;
   per = (per + BK - 1) / BK * BK;
@@ -708,6 +719,7 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
   }
   const float calpha = c * deq;
   float amax = 0.0f;
+  double mom[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int fm = 0; fm < 4; ++fm) {
 #pragma unroll
@@ -726,13 +738,27 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
             d.Af[o] = v[r];
             if (P != kF32) ((uint16_t*)d.As)[o] = f2bf(v[r]);
             amax = fmaxf(amax, fabsf(v[r]));
+          } else if (args.raw_a2) {
+            // learned path, step 1: keep A^2 and accumulate tr(A^k) partials;
+            // the combine kernel forms B once the schedule class is known
+            const float a2 = deq * x;
+            const float av = d.Af[o];
+            v[r] = a2;
+            d.A2f[o] = a2;
+            const double w = (ti == tj) ? 1.0 : 2.0;
+            if (ti == tj && i + r == j) mom[0] += (double)av;
+            mom[1] += w * (double)av * (double)av;
+            mom[2] += w * (double)av * (double)a2;
+            mom[3] += w * (double)a2 * (double)a2;
           } else {
             v[r] = b * d.Af[o] + calpha * x;
             if (P == kF32) ((float*)d.Bs)[o] = v[r];
             else ((uint16_t*)d.Bs)[o] = f2bf(v[r]);
           }
         }
-        if (ti != tj) {
+        if (ti != tj && kind == KIND_A2 && args.raw_a2) {
+          *(float4*)(d.A2f + (size_t)j * sp + i) = make_float4(v[0], v[1], v[2], v[3]);
+        } else if (ti != tj) {
           // mirrored tile: row j, columns i..i+3 (contiguous)
           const size_t o = (size_t)j * sp + i;
           if (kind == KIND_GRAM) {
@@ -748,6 +774,25 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
   }
   // the A^2 product of the same step quantises A with this maximum
   if (kind == KIND_GRAM && args.fp8) wave_amax_atomic(amax, d.scal + kScAmaxA + args.t);
+  if (kind == KIND_A2 && args.raw_a2) {
+    // fixed-order block reduction of the tile's moment partials
+    __shared__ double red[4][kThreads / 64];
+    const int tileid = tri_index(ti, tj, d.nb);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double x = mom[k];
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+      mom[k] = x;
+    }
+    __syncthreads();
+    if (lane == 0)
+      for (int k = 0; k < 4; ++k) red[k][wave] = mom[k];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      const int k = threadIdx.x;
+      d.mom[(size_t)tileid * 4 + k] = (red[k][0] + red[k][1]) + (red[k][2] + red[k][3]);
+    }
+  }
 }
 
 template <int P, int BT, bool LAST, typename A>
@@ -816,6 +861,7 @@ __global__ __launch_bounds__(kThreads, BT == 128 ? 2 : 1) void gemm_kernel(KArgs
     const int item = xcd_item(slot, args.total);
     const int mi = find_mat(args.offs, args.count, item);
     const MatDesc& d = args.descs[mi];
+    if (skip_matrix(args, d)) continue;
     const int local = item - args.offs[mi];
     Acc acc[4][4];
 #pragma unroll
@@ -889,6 +935,7 @@ __global__ __launch_bounds__(kThreads) void splitk_reduce_kernel(KArgs args) {
   for (int item = blockIdx.x; item < args.total; item += gridDim.x) {
     const int mi = find_mat(args.offs, args.count, item);
     const MatDesc& d = args.descs[mi];
+    if (skip_matrix(args, d)) continue;
     const int tile = item - args.offs[mi];
     const int split = KIND == KIND_GRAM ? d.gram_split : d.a2_split;
     int ti, tj;

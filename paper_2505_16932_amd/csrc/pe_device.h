@@ -59,6 +59,14 @@ struct MatDesc {
   uint32_t* cnt;    // [4]
   int32_t n_prep, syrk_nt, upd_nt, gram_split;
   int32_t a2_split, bt, g_vec, pad2;  // bt: block tile edge; g_vec: 16-byte loads of G
+  // learned l-predictor (null unless the call selects schedules per matrix)
+  int32_t* selp;    // schedule class of this matrix
+  int32_t* flagp;   // 1: the fallback re-run recomputes this matrix
+  float* A2f;       // sp x sp fp32: A^2 of step 1, before the class is known
+  double* mom;      // [syrk_nt][4] per-tile partial moments tr(A^k), k = 1..4
+  float* feat;      // [16] features (diagnostic copy)
+  float* est;       // [2]: estimate of ||X X^T - I||_2, flag
+  float* vec;       // power iteration vectors: v [sp], y [sp], w [Lp]
 };
 
 struct KArgs {
@@ -73,8 +81,20 @@ struct KArgs {
   int32_t norm_mode;
   int32_t tmax;          // rows of the selectable coefficient table
   float a, b, c;         // coefficients of step t (fixed schedule)
-  const float* sel_coef; // [n_sched][tmax][3] or nullptr
+  const float* sel_coef; // [n_sched][tmax][3] or nullptr: per-matrix class schedules
+  int32_t raw_a2;        // step-1 A^2 of the learned path: store A^2 and its moments
+  int32_t fallback;      // fallback re-run: skip matrices whose flag is 0
+  const float* mlp;      // predictor parameters (device) for the selection kernel
+  int32_t force_class;   // >= 0: use this class instead of the network's choice
+  int32_t fixed_class;
+  float tau;             // fallback threshold
+  int32_t est_phase;     // power-iteration phase selector
 };
+
+constexpr int kClasses = 8;
+constexpr int kFeat = 16;
+constexpr int kMlpH = 64;
+constexpr int kMlpParams = kFeat * kMlpH + kMlpH + kMlpH * kMlpH + kMlpH + kMlpH * kClasses + kClasses;
 
 // Device memory is filled from kernel arguments (copied at launch), so the
 // host needs neither pinned staging nor a synchronisation to upload tables.

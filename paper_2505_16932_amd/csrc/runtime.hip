@@ -12,6 +12,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,6 +23,15 @@
 namespace pe {
 hipError_t launch_put(const PutChunk& c, hipStream_t st);
 hipError_t launch_finalize(const KArgs& a, hipStream_t st);
+hipError_t launch_select(const KArgs& a, hipStream_t st);
+hipError_t launch_combine(int prec, const KArgs& a, hipStream_t st);
+hipError_t launch_est(const KArgs& a, int iters, hipStream_t st, const int32_t* offs_a, int total_a,
+                      const int32_t* offs_b, int total_b);
+hipError_t launch_mlp_forward(const float* params, const float* feats, int B, float* logits,
+                              hipStream_t st);
+hipError_t launch_mlp_grad(const float* params, const float* feats, const int32_t* labels, int B,
+                           float* part, float* part_loss, float* grad_out, float* loss_out,
+                           float* upd_params, float* m, float* v, int step, float lr, hipStream_t st);
 hipError_t launch_quantize(const void* x, int x_bf16, uint8_t* q, int64_t n, float scale,
                            hipStream_t st);
 hipError_t launch_prep(int prec, const KArgs& a, int grid_cap, hipStream_t st);
@@ -34,7 +45,13 @@ namespace {
 
 thread_local std::string g_last_error;
 
-enum Phase { PH_PREP = 0, PH_GRAM, PH_A2, PH_UPD, PH_RGRAM, PH_RA2, PH_N };
+enum Phase { PH_PREP = 0, PH_GRAM, PH_A2, PH_UPD, PH_RGRAM, PH_RA2, PH_COMBINE, PH_EST_A, PH_EST_B, PH_N };
+
+constexpr double kClassEll[kClasses] = {1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5};
+constexpr int kFixedClass = 4;
+constexpr int kEstIters = 8;
+
+bool learned_mode(const pe_opts* o) { return o->predictor != nullptr || o->force_class >= 0; }
 
 constexpr int kGemmGridCap = 512;       // 128-tile kernel: 2 resident blocks per CU x 256 CUs
 constexpr int kGemmGridCapLarge = 256;  // 256-tile kernel: 1 resident block per CU
@@ -57,7 +74,7 @@ struct Layout {
   std::vector<int32_t> offs[PH_N];      // count + 1 each
   int32_t totals[PH_N] = {0};
   size_t bytes = 0;
-  size_t descs_off = 0, offs_off = 0;
+  size_t descs_off = 0, offs_off = 0, coef_off = 0;
   int bt = kTileSmall;
 };
 
@@ -82,6 +99,8 @@ pe_status check_opts(const pe_opts* o) {
   }
   for (int i = 0; i < 3 * o->T; ++i)
     if (!std::isfinite(o->abc[i])) return PE_EINVAL;
+  if (o->force_class < -1 || o->force_class >= kClasses) return PE_EINVAL;
+  if (!std::isfinite(o->fallback_tau)) return PE_EINVAL;
   return PE_OK;
 }
 
@@ -91,9 +110,44 @@ int prec_of(const pe_opts* o) { return o->compute == PE_COMPUTE_F32 ? kF32 : kBF
 // halves the LDS and L2 traffic per flop of the 128 x 128 tile, but pads s and
 // L to multiples of 256 and yields 4x fewer tiles.  Used on the bf16 paths when
 // every matrix has s >= 512 and the update has at least one tile per CU.
+// Autotuned choices: shape class -> tile id (1 = 128, 2 = 256), loaded from the
+// text table written by the autotuner.  A class is (precision, s bucket, aspect
+// bucket); see shape_class().
+std::mutex g_tab_mu;
+std::map<std::string, int> g_tile_table;
+
+std::string shape_class(int prec, int64_t s, int64_t L) {
+  static const int64_t sb[] = {256, 512, 1024, 2048, 4096};
+  int i = 0;
+  while (i < 5 && s > sb[i]) ++i;
+  const double a = (double)L / (double)s;
+  const int ab = a <= 1.5 ? 1 : (a <= 4.0 ? 4 : 16);
+  char buf[64];
+  snprintf(buf, sizeof buf, "%s_s%lld_a%d", prec == kF32 ? "f32" : "bf16",
+           (long long)(i < 5 ? sb[i] : 8192), ab);
+  return buf;
+}
+
 int choose_tile(int count, const pe_matrix* mats, const pe_opts* o) {
   if (o->tile == 1) return kTileSmall;
   if (o->tile == 2) return kTileLarge;
+  {
+    // autotuned: every matrix votes for its class's tile with its flop count
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    if (!g_tile_table.empty()) {
+      double w[3] = {0, 0, 0};
+      bool all_known = true;
+      for (int i = 0; i < count; ++i) {
+        const pe_matrix& m = mats[i];
+        if (m.m <= 0 || m.n <= 0) continue;
+        const int64_t s = std::min(m.m, m.n), L = std::max(m.m, m.n);
+        auto it = g_tile_table.find(shape_class(prec_of(o), s, L));
+        if (it == g_tile_table.end()) { all_known = false; break; }
+        w[it->second] += 3.0 * (double)s * s * L + (double)s * s * s;
+      }
+      if (all_known && (w[1] > 0 || w[2] > 0)) return w[2] > w[1] ? kTileLarge : kTileSmall;
+    }
+  }
   if (prec_of(o) == kF32) return kTileSmall;
   int64_t upd_tiles = 0;
   bool any = false;
@@ -144,6 +198,9 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
   off = align_up(off + sizeof(MatDesc) * (size_t)std::max(count, 1));
   L->offs_off = off;
   off = align_up(off + sizeof(int32_t) * (size_t)PH_N * (count + 1));
+  const bool learned = learned_mode(o);
+  L->coef_off = off;
+  if (learned) off = align_up(off + sizeof(float) * kClasses * 3 * (size_t)o->T);
   for (int i = 0; i < count; ++i) {
     const pe_matrix& m = mats[i];
     const Shape& q = sh[i];
@@ -199,6 +256,16 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
       d.red = (double*)take((size_t)q.prep * 12 + 16);
       d.scal = (float*)take(kScN * 4);
       d.cnt = (uint32_t*)take(64);  // reserved
+      if (learned) {
+        int32_t* ints = (int32_t*)take(64);
+        d.selp = ints;
+        d.flagp = ints ? ints + 1 : nullptr;
+        d.A2f = (float*)take(A * 4);
+        d.mom = (double*)take((size_t)q.syrk * 4 * 8);
+        d.feat = (float*)take(kFeat * 4);
+        d.est = (float*)take(64);
+        d.vec = (float*)take(((size_t)2 * q.sp + q.Lp) * 4);
+      }
     }
     L->descs.push_back(d);
     auto push = [&](int ph, int n) { L->offs[ph].push_back(L->offs[ph].back() + n); };
@@ -208,6 +275,16 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
     push(PH_UPD, q.syrk ? q.upd : 0);
     push(PH_RGRAM, (q.syrk && d.gram_split > 1) ? q.syrk : 0);
     push(PH_RA2, (q.syrk && d.a2_split > 1) ? q.syrk : 0);
+    push(PH_COMBINE, (q.syrk && learned) ? (int)q.sp : 0);
+    // power iteration: w = X^T v (length L), then y = X w (length s); a product
+    // along the rows of the caller's m x n output takes one wave per row (4 per
+    // block), one across its columns 64 columns per block
+    {
+      const bool t = m.m > m.n;
+      const int rows4 = (int)((m.m + 3) / 4), cols64 = (int)((m.n + 63) / 64);
+      push(PH_EST_A, (q.syrk && learned) ? (t ? rows4 : cols64) : 0);
+      push(PH_EST_B, (q.syrk && learned) ? (t ? cols64 : rows4) : 0);
+    }
   }
   for (int p = 0; p < PH_N; ++p) L->totals[p] = L->offs[p].back();
   L->bytes = off;
@@ -254,6 +331,11 @@ struct pe_plan {
   int T = 0;
   int norm_mode = 0;
   std::vector<float> abc;
+  bool learned = false;
+  const float* mlp = nullptr;
+  int force_class = -1;
+  float tau = 0.0f;
+  float* d_coef = nullptr;     // [classes][T][3]
   Layout L;
   MatDesc* d_descs = nullptr;
   int32_t* d_offs = nullptr;
@@ -271,7 +353,22 @@ pe_status upload(pe_plan* p, char* ws, hipStream_t st) {
   if (s != PE_OK) return s;
   std::vector<int32_t> offs;
   for (int ph = 0; ph < PH_N; ++ph) offs.insert(offs.end(), p->L.offs[ph].begin(), p->L.offs[ph].end());
-  return put_words(p->d_offs, offs.data(), offs.size() * 4, st);
+  s = put_words(p->d_offs, offs.data(), offs.size() * 4, st);
+  if (s != PE_OK || !p->learned) return s;
+  // schedule table of the classes: class 4 is the caller's schedule
+  std::vector<float> tab((size_t)kClasses * p->T * 3);
+  std::vector<double> abc(3 * (size_t)p->T);
+  for (int c = 0; c < kClasses; ++c) {
+    if (c == kFixedClass) {
+      for (int i = 0; i < 3 * p->T; ++i) tab[(size_t)c * 3 * p->T + i] = p->abc[i];
+      continue;
+    }
+    s = pe_coeffs(kClassEll[c], p->T, nullptr, abc.data(), nullptr, nullptr, nullptr);
+    if (s != PE_OK) return s;
+    for (int i = 0; i < 3 * p->T; ++i) tab[(size_t)c * 3 * p->T + i] = (float)abc[i];
+  }
+  p->d_coef = (float*)(ws + p->L.coef_off);
+  return put_words(p->d_coef, tab.data(), tab.size() * 4, st);
 }
 
 KArgs base_args(const pe_plan* p) {
@@ -281,6 +378,13 @@ KArgs base_args(const pe_plan* p) {
   a.count = p->count;
   a.norm_mode = p->norm_mode;
   a.tmax = p->T;
+  if (p->learned) {
+    a.sel_coef = p->d_coef;
+    a.mlp = p->mlp;
+    a.force_class = p->force_class;
+    a.fixed_class = kFixedClass;
+    a.tau = p->tau;
+  }
   return a;
 }
 
@@ -297,8 +401,9 @@ void set_step(const pe_plan* p, KArgs* a, int t) {
   a->c = p->abc[3 * t + 2];
 }
 
-pe_status enqueue_norm(const pe_plan* p, hipStream_t st) {
+pe_status enqueue_norm(const pe_plan* p, hipStream_t st, int fallback = 0) {
   KArgs a = base_args(p);
+  a.fallback = fallback;
   set_phase(p, &a, PH_PREP);
   hipError_t e = launch_prep(p->prec, a, kPrepGridCap, st);
   if (e != hipSuccess) return hip_fail(e, "prep launch");
@@ -307,7 +412,7 @@ pe_status enqueue_norm(const pe_plan* p, hipStream_t st) {
 }
 
 // kind: 0 Gram, 1 A^2 + combine, 2 update
-pe_status enqueue_gemm(const pe_plan* p, int t, int kind, hipStream_t st) {
+pe_status enqueue_gemm(const pe_plan* p, int t, int kind, hipStream_t st, int fallback = 0) {
   static const int ph_main[3] = {PH_GRAM, PH_A2, PH_UPD};
   static const int ph_red[3] = {PH_RGRAM, PH_RA2, -1};
   static const char* names[3] = {"gram launch", "a2 launch", "update launch"};
@@ -316,6 +421,9 @@ pe_status enqueue_gemm(const pe_plan* p, int t, int kind, hipStream_t st) {
   set_phase(p, &a, ph_main[kind]);
   a.fp8 = t < p->fp8_steps;
   a.fp8_next = t + 1 < p->fp8_steps;
+  a.fallback = fallback;
+  // learned path, step 1: A^2 and its moments are kept until the class is chosen
+  a.raw_a2 = p->learned && !fallback && t == 0 && kind == 1;
   // Gram-side products of the FP8 steps run the e4m3 kernels; updates stay bf16
   const int prec = (a.fp8 && kind != 2) ? kFP8 : p->prec;
   hipError_t e = launch_gemm(prec, p->L.bt, kind, a, p->L.bt == kTileLarge ? kGemmGridCapLarge : kGemmGridCap, st);
@@ -328,14 +436,40 @@ pe_status enqueue_gemm(const pe_plan* p, int t, int kind, hipStream_t st) {
   return PE_OK;
 }
 
-pe_status enqueue(const pe_plan* p, hipStream_t st) {
-  if (p->L.totals[PH_PREP] == 0) return PE_OK;
-  pe_status s = enqueue_norm(p, st);
+// learned path between step 1's A^2 and its update: choose the class, form B
+pe_status enqueue_select(const pe_plan* p, hipStream_t st) {
+  KArgs a = base_args(p);
+  set_step(p, &a, 0);
+  hipError_t e = launch_select(a, st);
+  if (e != hipSuccess) return hip_fail(e, "select launch");
+  set_phase(p, &a, PH_COMBINE);
+  if ((e = launch_combine(p->prec, a, st)) != hipSuccess) return hip_fail(e, "combine launch");
+  return PE_OK;
+}
+
+pe_status enqueue_steps(const pe_plan* p, hipStream_t st, int fallback) {
+  pe_status s = enqueue_norm(p, st, fallback);
   if (s != PE_OK) return s;
   for (int t = 0; t < p->T; ++t)
-    for (int kind = 0; kind < 3; ++kind)
-      if ((s = enqueue_gemm(p, t, kind, st)) != PE_OK) return s;
+    for (int kind = 0; kind < 3; ++kind) {
+      if ((s = enqueue_gemm(p, t, kind, st, fallback)) != PE_OK) return s;
+      if (p->learned && !fallback && t == 0 && kind == 1 && (s = enqueue_select(p, st)) != PE_OK)
+        return s;
+    }
   return PE_OK;
+}
+
+pe_status enqueue(const pe_plan* p, hipStream_t st) {
+  if (p->L.totals[PH_PREP] == 0) return PE_OK;
+  pe_status s = enqueue_steps(p, st, 0);
+  if (s != PE_OK || !p->learned || !(p->tau > 0.0f)) return s;
+  // estimate ||X X^T - I||_2 of every result; re-run the failed ones with class 4
+  KArgs a = base_args(p);
+  hipError_t e = launch_est(a, kEstIters, st, p->d_offs + (size_t)PH_EST_A * (p->count + 1),
+                            p->L.totals[PH_EST_A], p->d_offs + (size_t)PH_EST_B * (p->count + 1),
+                            p->L.totals[PH_EST_B]);
+  if (e != hipSuccess) return hip_fail(e, "estimate launch");
+  return enqueue_steps(p, st, 1);
 }
 
 pe_status plan_init(pe_plan* p, int count, const pe_matrix* mats, const pe_opts* o, void* ws,
@@ -349,6 +483,10 @@ pe_status plan_init(pe_plan* p, int count, const pe_matrix* mats, const pe_opts*
   p->norm_mode = o->norm_mode;
   p->abc.resize(3 * o->T);
   for (int i = 0; i < 3 * o->T; ++i) p->abc[i] = (float)o->abc[i];
+  p->learned = learned_mode(o);
+  p->mlp = o->predictor;
+  p->force_class = o->force_class;
+  p->tau = o->fallback_tau;
   Layout sizing;
   build_layout(count, mats, o, nullptr, &sizing);
   if (sizing.totals[PH_PREP] == 0) return PE_OK;  // nothing but empty matrices
@@ -449,6 +587,75 @@ pe_status pe_plan_destroy(pe_plan* p) {
   return PE_OK;
 }
 
+pe_status pe_plan_selection(pe_plan* p, int32_t* classes, float* feats, float* est, int32_t* flags) {
+  g_last_error.clear();
+  if (!p) return PE_EINVAL;
+  if (!p->learned) return PE_EINVAL;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "selection sync");
+  for (int i = 0; i < p->count; ++i) {
+    const MatDesc& d = p->L.descs[i];
+    int32_t ints[2] = {-1, 0};
+    float f[kFeat] = {0}, es[2] = {0, 0};
+    if (d.selp) {
+      if ((e = hipMemcpy(ints, d.selp, sizeof ints, hipMemcpyDeviceToHost)) != hipSuccess ||
+          (e = hipMemcpy(f, d.feat, sizeof f, hipMemcpyDeviceToHost)) != hipSuccess ||
+          (e = hipMemcpy(es, d.est, sizeof es, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "selection copy");
+    }
+    if (classes) classes[i] = ints[0];
+    if (flags) flags[i] = ints[1];
+    if (feats) memcpy(feats + (size_t)i * kFeat, f, sizeof f);
+    if (est) est[i] = es[0];
+  }
+  return PE_OK;
+}
+
+size_t pe_mlp_workspace_size(int32_t B) {
+  if (B <= 0) return 0;
+  const size_t nblk = (size_t)(B + 63) / 64;
+  return align_up(nblk * kMlpParams * 4) + align_up(nblk * 4);
+}
+
+pe_status pe_mlp_forward(const float* params, const float* feats, int32_t B, float* logits,
+                         void* stream) {
+  g_last_error.clear();
+  if (B < 0 || (B > 0 && (!params || !feats || !logits))) return PE_EINVAL;
+  if (B == 0) return PE_OK;
+  hipError_t e = launch_mlp_forward(params, feats, B, logits, (hipStream_t)stream);
+  return e == hipSuccess ? PE_OK : hip_fail(e, "mlp forward");
+}
+
+static pe_status mlp_grad_common(const float* params, const float* feats, const int32_t* labels,
+                                 int32_t B, float* grad, float* loss, float* upd, float* m, float* v,
+                                 int32_t step, float lr, void* ws, size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  if (B <= 0 || !params || !feats || !labels) return PE_EINVAL;
+  const size_t need = pe_mlp_workspace_size(B);
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) return PE_EWORKSPACE;
+  const size_t nblk = (size_t)(B + 63) / 64;
+  float* part = (float*)ws;
+  float* part_loss = (float*)((char*)ws + align_up(nblk * kMlpParams * 4));
+  hipError_t e = launch_mlp_grad(params, feats, labels, B, part, part_loss, grad, loss, upd, m, v,
+                                 step, lr, (hipStream_t)stream);
+  return e == hipSuccess ? PE_OK : hip_fail(e, "mlp grad");
+}
+
+pe_status pe_mlp_grad(const float* params, const float* feats, const int32_t* labels, int32_t B,
+                      float* grad, float* loss, void* ws, size_t ws_bytes, void* stream) {
+  if (!grad) return PE_EINVAL;
+  return mlp_grad_common(params, feats, labels, B, grad, loss, nullptr, nullptr, nullptr, 0, 0.0f,
+                         ws, ws_bytes, stream);
+}
+
+pe_status pe_mlp_train_step(float* params, float* m, float* v, int32_t step, float lr,
+                            const float* feats, const int32_t* labels, int32_t B, float* loss,
+                            void* ws, size_t ws_bytes, void* stream) {
+  if (!m || !v || step < 1 || !(lr > 0.0f) || !std::isfinite(lr)) return PE_EINVAL;
+  return mlp_grad_common(params, feats, labels, B, nullptr, loss, params, m, v, step, lr, ws,
+                         ws_bytes, stream);
+}
+
 pe_status pe_quantize_e4m3(const void* x, int32_t x_dtype, void* q, int64_t n, float scale,
                            void* stream) {
   g_last_error.clear();
@@ -472,7 +679,31 @@ const char* pe_tile_name(int32_t tile_id) {
 
 pe_status pe_tile_table_load(const char* path) {
   if (!path) return PE_EINVAL;
-  return PE_EUNSUPPORTED;
+  FILE* f = fopen(path, "r");
+  if (!f) return PE_EINVAL;
+  std::map<std::string, int> tab;
+  char line[256];
+  while (fgets(line, sizeof line, f)) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    char cls[128];
+    int id = 0;
+    if (sscanf(line, "%127s %d", cls, &id) != 2 || id < 1 || id > 2) {
+      fclose(f);
+      return PE_EINVAL;
+    }
+    tab[cls] = id;
+  }
+  fclose(f);
+  std::lock_guard<std::mutex> lk(g_tab_mu);
+  g_tile_table.swap(tab);
+  return PE_OK;
+}
+
+const char* pe_shape_class(int32_t compute, int64_t m, int64_t n) {
+  thread_local std::string s;
+  if (m <= 0 || n <= 0) return "";
+  s = shape_class(compute == PE_COMPUTE_F32 ? kF32 : kBF16, std::min(m, n), std::max(m, n));
+  return s.c_str();
 }
 
 const char* pe_status_string(pe_status st) {

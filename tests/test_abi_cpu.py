@@ -73,7 +73,7 @@ def test_coeffs_invalid_arguments():
 
 def _opts(T=5, compute=1, fp8=0):
     abc = np.tile(np.array(S.NS5), (T, 1)).reshape(-1).copy()
-    o = pe.Opts(T, abc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), compute, fp8, 0, 0)
+    o = pe.Opts(T, abc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), compute, fp8, 0, 0, None, -1, 0.0)
     return o, abc
 
 
@@ -103,3 +103,63 @@ def test_workspace_and_argument_checks():
     assert L.pe_polar(ctypes.byref(z), ctypes.byref(o), None, 0, None) == 0
     assert L.pe_polar_batched(0, None, ctypes.byref(o), None, 0, None) == 0
     assert L.pe_status_string(4) == b"workspace missing, too small or not 256-byte aligned"
+
+
+def test_learned_features_match_oracle_definition():
+    """The host feature code used for training (product side) and the oracle's
+    definition agree (both restate the same 16 features)."""
+    from oracle import mlp as OM
+    from paper_2505_16932_amd import learned as PL
+    r = np.random.default_rng(3)
+    for _ in range(20):
+        s, L = int(r.integers(2, 3000)), int(r.integers(2, 9000))
+        m = np.sort(r.uniform(1e-9, 1.0, 4))[::-1] ** np.array([1, 2, 3, 4])
+        assert np.allclose(PL.features(s, L, m), OM.features(s, L, m), rtol=1e-12, atol=1e-12)
+
+
+def test_learned_labels_match_oracle():
+    from oracle import mlp as OM
+    from paper_2505_16932_amd import learned as PL
+    F, Y, E = PL.build_dataset(40, seed=11, T=5)
+    rng = np.random.Generator(np.random.PCG64(11))
+    scheds = OM.class_schedules(5)
+    for i in range(40):
+        m, n, sig, _ = PL.sample_spectrum(rng)
+        sh = sig / (1.01 * np.sqrt(np.sum(sig * sig)) + 1e-7)
+        e = OM.class_errors(sh, 5, scheds)
+        # the two schedule builders differ by up to ~1e-7 relative on the
+        # near-degenerate steps of the larger-l schedules (4x4 conditioning)
+        assert np.allclose(E[i], e, rtol=1e-6, atol=1e-8)
+        assert e[Y[i]] <= e.min() * (1 + 1e-6) + 1e-8
+        assert np.allclose(F[i], OM.features(min(m, n), max(m, n), OM.moments_from_spectrum(sh)),
+                           rtol=1e-5, atol=1e-5)
+
+
+def test_tile_table_drives_the_tile_choice(tmp_path):
+    """An autotuned table entry changes the padding (128 vs 256) and so the
+    workspace size; malformed tables are rejected; unknown classes keep the
+    built-in choice."""
+    L = pe.lib()
+    o, keep = _opts()
+    m = pe.Matrix(16, 32, 600, 1000, 1000, 1000, 1, 1)
+    cls = L.pe_shape_class(1, 600, 1000).decode()
+    assert cls == "bf16_s1024_a4"
+    t = tmp_path / "tab.txt"
+    sizes = {}
+    for tile in (1, 2):
+        t.write_text(f"# test\n{cls} {tile}  # comment\n")
+        assert L.pe_tile_table_load(str(t).encode()) == 0
+        sizes[tile] = L.pe_workspace_size(1, ctypes.byref(m), ctypes.byref(o))
+    assert sizes[2] > sizes[1]
+    t.write_text("bf16_s256_a1 2\n")
+    assert L.pe_tile_table_load(str(t).encode()) == 0
+    # 600 x 1000 is not in this table: built-in choice (s >= 512 but few tiles -> 128)
+    assert L.pe_workspace_size(1, ctypes.byref(m), ctypes.byref(o)) == sizes[1]
+    t.write_text("bf16_s256_a1 7\n")
+    assert L.pe_tile_table_load(str(t).encode()) == 1
+    assert L.pe_tile_table_load(b"/nonexistent/table") == 1
+    # restore the shipped table (if any) for later tests
+    import os
+    shipped = os.path.join(os.path.dirname(pe.LIB_PATH), "tile_table.txt")
+    t.write_text("# empty\n")
+    assert L.pe_tile_table_load((shipped if os.path.exists(shipped) else str(t)).encode()) == 0
