@@ -164,7 +164,8 @@ pe_status pe_plan_destroy(pe_plan* plan);
  * 2 = A^2 + combine (with its reduction), 3 = update X = aX + BX.  The phase
  * reads whatever the plan's buffers hold (run pe_plan_launch first); the
  * buffers are left in an unspecified state, the caller's X untouched unless
- * step = T-1 and phase = 3.  PE_EINVAL for a bad step or phase. */
+ * step = T-1 and phase = 3.  PE_EINVAL for a bad step or phase;
+ * PE_EUNSUPPORTED for a plan with the learned choice of l. */
 pe_status pe_plan_launch_phase(pe_plan* plan, int32_t step, int32_t phase, void* stream);
 
 /* The e4m3 conversion of the FP8 path, for checking it: q[i] = e4m3(x[i] * scale)

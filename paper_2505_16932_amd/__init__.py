@@ -370,7 +370,8 @@ class Plan:
 
     def __init__(self, Gs, outs=None, T: int = 5, ell: float = 1e-3, abc=None, compute: str = "bf16",
                  out_dtype=None, fp8_steps: int = 0, norm_mode: int = 0, tile: int = 0, stream=None,
-                 predictor=None, force_class: int = -1, fallback_tau: float = 0.0):
+                 predictor=None, force_class: int = -1, fallback_tau: float = 0.0,
+                 ws_fill=None):
         import torch
         self.Gs = list(Gs)
         self.outs = outs if outs is not None else [
@@ -388,6 +389,9 @@ class Plan:
         if self.ws_bytes == 0:
             _check(1, "pe_workspace_size")
         self._ws_buf, self._ws = _workspace(self.ws_bytes, self.Gs[0].device)
+        if ws_fill is not None:
+            # the library must not depend on the workspace's prior contents
+            self._ws_buf.fill_(int(ws_fill) & 0xFF)
         h = ctypes.c_void_p()
         _check(L.pe_plan_create(len(self.Gs), self._mats, ctypes.byref(o), ctypes.c_void_p(self._ws),
                                 self.ws_bytes, _stream(stream), ctypes.byref(h)), "pe_plan_create")

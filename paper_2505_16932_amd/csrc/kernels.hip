@@ -77,7 +77,12 @@ __device__ __forceinline__ bool skip_matrix(const KArgs& args, const MatDesc& d)
 __device__ __forceinline__ void step_coef(const KArgs& args, const MatDesc& d, float* a, float* b,
                                           float* c) {
   if (args.sel_coef) {
-    const float* p = args.sel_coef + ((size_t)(*d.selp) * args.tmax + args.t) * 3;
+    // the class slot is written before any product that reads coefficients
+    // (finalize: fixed class; select: the chosen one); an out-of-range value
+    // still falls back to the fixed class instead of leaving the table
+    int cls = *d.selp;
+    if (cls < 0 || cls >= kClasses) cls = args.fixed_class;
+    const float* p = args.sel_coef + ((size_t)cls * args.tmax + args.t) * 3;
     *a = p[0]; *b = p[1]; *c = p[2];
   } else {
     *a = args.a; *b = args.b; *c = args.c;
@@ -234,6 +239,12 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(KArgs args) {
       d.scal[kScFro] = (float)fro;
     }
     for (int i = kScAmaxX + tid; i < kScN; i += kThreads) d.scal[i] = 0.0f;
+    // learned path, first pass: the class slot holds the fixed class until the
+    // selection kernel overwrites it, and no matrix is marked for the re-run
+    if (d.selp && !args.fallback && tid == 0) {
+      *d.selp = args.fixed_class;
+      *d.flagp = 0;
+    }
   }
 }
 
@@ -710,8 +721,9 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const size_t sp = d.sp;
-  float a, b, c;
-  step_coef(args, d, &a, &b, &c);
+  // only B = bA + cA^2 needs the step's coefficients
+  float a = 0.0f, b = 0.0f, c = 0.0f;
+  if (kind == KIND_A2 && !args.raw_a2) step_coef(args, d, &a, &b, &c);
   float alpha = deq;
   if (kind == KIND_GRAM && args.t == 0) {
     const float sg = d.scal[kScScale];

@@ -258,7 +258,9 @@ __global__ __launch_bounds__(256) void combine_kernel(KArgs args) {
     }
     const MatDesc& d = args.descs[lo];
     const int row = item - args.offs[lo];  // one row of the s x s block per item
-    const float* cf = args.sel_coef + ((size_t)(*d.selp) * args.tmax + args.t) * 3;
+    int cls = *d.selp;
+    if (cls < 0 || cls >= kClasses) cls = args.fixed_class;
+    const float* cf = args.sel_coef + ((size_t)cls * args.tmax + args.t) * 3;
     const float b = cf[1], c = cf[2];
     const size_t base = (size_t)row * d.sp;
     for (int j = threadIdx.x; j < d.sp; j += blockDim.x) {

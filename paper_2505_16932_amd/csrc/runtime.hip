@@ -572,6 +572,8 @@ pe_status pe_plan_launch(pe_plan* p, void* stream, int32_t use_graph) {
 pe_status pe_plan_launch_phase(pe_plan* p, int32_t step, int32_t phase, void* stream) {
   g_last_error.clear();
   if (!p || step < 0 || step >= p->T || phase < 0 || phase > 3) return PE_EINVAL;
+  // a learned plan's step 1 also selects the class between its phases
+  if (p->learned) return PE_EUNSUPPORTED;
   if (p->L.totals[PH_PREP] == 0) return PE_OK;
   hipStream_t st = (hipStream_t)stream;
   if (phase == 0) return enqueue_norm(p, st);

@@ -137,6 +137,32 @@ def test_selection_in_plan_matches_oracle(pe, trained):
     plan.close()
 
 
+@pytest.mark.parametrize("fill", [0x00, 0x3F, 0xFF])
+def test_learned_plan_ignores_workspace_contents(pe, fill):
+    """The workspace needs no initialisation: whatever it held before (here
+    every byte = fill, i.e. class slots reading 0, 0x3F3F3F3F or -1), a plan
+    with a forced class gives the plain call's result with that class's
+    schedule, eagerly and on graph replays."""
+    import torch
+    G, _ = _materialise(20, 320, 640, synth.spectrum_powerlaw(320, 1.0))
+    abc4 = OS.greedy_schedule(1e-3, 5).abc
+    print(f"[learned] workspace fill 0x{fill:02x}", flush=True)
+    plan = pe.Plan([G], T=5, abc=abc4, compute="bf16", force_class=2, out_dtype=torch.float32,
+                   ws_fill=fill)
+    ref = pe.polar(G, T=5, abc=pe.coeffs(OM.CLASS_ELL[2], 5).abc, compute="bf16",
+                   out_dtype=torch.float32)
+    plan.launch(graph=False)
+    torch.cuda.synchronize()
+    assert relf(to_np(plan.outs[0]), to_np(ref)) <= 1e-6
+    cls, _, _, flags = plan.selection()
+    assert cls.tolist() == [2] and flags.tolist() == [0]
+    for _ in range(2):
+        plan.launch(graph=True)
+        torch.cuda.synchronize()
+        assert relf(to_np(plan.outs[0]), to_np(ref)) <= 1e-6
+    plan.close()
+
+
 def test_fallback_fires_and_matches_fixed_schedule(pe):
     """Forcing the largest l on a spectrum reaching 1e-5 leaves small singular
     values unconverged: the ||X X^T - I|| estimate exceeds the threshold and the
@@ -147,7 +173,7 @@ def test_fallback_fires_and_matches_fixed_schedule(pe):
     G2, v2 = _materialise(11, 384, 768, np.linspace(1.0, 0.5, 384))
     abc4 = OS.greedy_schedule(1e-3, 5).abc
     plan = pe.Plan([G1, G2], T=5, abc=abc4, compute="bf16", force_class=0, fallback_tau=0.5,
-                   out_dtype=torch.float32)
+                   out_dtype=torch.float32, ws_fill=0x3F)
     plan.launch(graph=False)
     torch.cuda.synchronize()
     cls, feats, est, flags = plan.selection()
