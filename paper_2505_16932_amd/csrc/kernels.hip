@@ -714,6 +714,30 @@ __device__ __forceinline__ int acc_col(int wn, int fn, int lane) {
   return wn * (BT / 2) + fn * F + (lane % F);
 }
 
+// The epilogues read one FP32 matrix (A for B = bA + cA^2, X for X = aX + BX)
+// at the accumulator positions and write others, possibly the same buffer.
+// A lane's inputs of one fragment row fm (4 fragments) are loaded before the
+// stores of the previous row are issued, so the loads of a row overlap instead
+// of each one waiting behind the stores the compiler must keep ahead of it.
+template <int BT>
+struct FragRow {
+  float x[4][TileCfg<BT>::RG][4];  // [fn][row group][r]
+};
+
+template <int BT>
+__device__ __forceinline__ void load_frag_row(const float* __restrict__ src, size_t ld, int row0,
+                                              int col0, int wm, int wn, int fm, int lane,
+                                              FragRow<BT>& f) {
+#pragma unroll
+  for (int fn = 0; fn < 4; ++fn)
+#pragma unroll
+    for (int g = 0; g < TileCfg<BT>::RG; ++g) {
+      const size_t o = (size_t)(row0 + acc_row<BT>(wm, fm, g, lane)) * ld + col0 + acc_col<BT>(wn, fn, lane);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) f.x[fn][g][r] = src[o + (size_t)r * ld];
+    }
+}
+
 template <int P, int BT, typename A>
 __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, int kind, int ti,
                                          int tj, float deq, const A (&acc)[4][4]) {
@@ -732,8 +756,13 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
   const float calpha = c * deq;
   float amax = 0.0f;
   double mom[4] = {0.0, 0.0, 0.0, 0.0};
+  const bool reads_a = kind == KIND_A2;
+  FragRow<BT> pre[2];
+  if (reads_a) load_frag_row<BT>(d.Af, sp, ti * BT, tj * BT, wm, wn, 0, lane, pre[0]);
 #pragma unroll
   for (int fm = 0; fm < 4; ++fm) {
+    if (reads_a && fm + 1 < 4) load_frag_row<BT>(d.Af, sp, ti * BT, tj * BT, wm, wn, fm + 1, lane, pre[(fm + 1) & 1]);
+    const FragRow<BT>& cur = pre[fm & 1];
 #pragma unroll
     for (int fn = 0; fn < 4; ++fn) {
 #pragma unroll
@@ -754,7 +783,7 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
             // learned path, step 1: keep A^2 and accumulate tr(A^k) partials;
             // the combine kernel forms B once the schedule class is known
             const float a2 = deq * x;
-            const float av = d.Af[o];
+            const float av = cur.x[fn][g][r];
             v[r] = a2;
             d.A2f[o] = a2;
             const double w = (ti == tj) ? 1.0 : 2.0;
@@ -763,7 +792,7 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
             mom[2] += w * (double)av * (double)a2;
             mom[3] += w * (double)a2 * (double)a2;
           } else {
-            v[r] = b * d.Af[o] + calpha * x;
+            v[r] = b * cur.x[fn][g][r] + calpha * x;
             if (P == kF32) ((float*)d.Bs)[o] = v[r];
             else ((uint16_t*)d.Bs)[o] = f2bf(v[r]);
           }
@@ -819,8 +848,12 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
   const size_t Lp = d.Lp, sp = d.sp;
   void* XTn = (args.t & 1) ? d.XT0 : d.XT1;
   float amax = 0.0f;
+  FragRow<BT> pre[2];
+  load_frag_row<BT>(d.Xf, Lp, tm * BT, tn * BT, wm, wn, 0, lane, pre[0]);
 #pragma unroll
   for (int fm = 0; fm < 4; ++fm) {
+    if (fm + 1 < 4) load_frag_row<BT>(d.Xf, Lp, tm * BT, tn * BT, wm, wn, fm + 1, lane, pre[(fm + 1) & 1]);
+    const FragRow<BT>& cur = pre[fm & 1];
 #pragma unroll
     for (int fn = 0; fn < 4; ++fn) {
 #pragma unroll
@@ -829,10 +862,7 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
         const int n = tn * BT + acc_col<BT>(wn, fn, lane);
         float v[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const size_t o = (size_t)(i + r) * Lp + n;
-          v[r] = alpha * (a * d.Xf[o] + acc[fm][fn][4 * g + r]);
-        }
+        for (int r = 0; r < 4; ++r) v[r] = alpha * (a * cur.x[fn][g][r] + acc[fm][fn][4 * g + r]);
         if constexpr (!LAST) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
