@@ -416,6 +416,17 @@ __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
+// Workgroup barrier that orders LDS accesses for the compiler without the
+// memory fences of __syncthreads (which would also wait for every
+// outstanding global load): the empty asm statements with a memory clobber
+// keep the compiler from moving loads or stores across the s_barrier; the
+// hardware ordering comes from the explicit waits placed before it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 template <int BT>
 __device__ __forceinline__ void dl_issue_stage(const PE_GLOBAL uint16_t* P, const PE_GLOBAL uint16_t* Q,
                                                int64_t ld, int kofs, char* slot, int wave, int lane) {
@@ -466,6 +477,39 @@ __device__ __forceinline__ void dl_mma_stage(const char* sA, const char* sB, int
   }
 }
 
+// s_waitcnt lgkmcnt(0) with vmcnt and expcnt left at their maxima
+__device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+// Fragments of one 16-deep k-step of the 256 tile (32x32x16 MFMA): rows
+// lane % 32 of four 32-row fragments per operand, 16-byte chunk
+// 2 * sub + lane / 32 of the stage's 64-byte row.
+struct Frags32 {
+  u32x4 a[4], b[4];
+};
+
+__device__ __forceinline__ void dl_read_frags32(const char* stage, int sub, int wm, int wn, int lane,
+                                                Frags32& f) {
+  constexpr int OPB = DlCfg<256>::OPB;
+  const int lc = 2 * sub + (lane >> 5);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int ra = wm * 128 + i * 32 + (lane & 31);
+    const int rb = wn * 128 + i * 32 + (lane & 31);
+    f.a[i] = *(const u32x4*)(stage + ra * 64 + dl_swz(ra, lc) * 16);
+    f.b[i] = *(const u32x4*)(stage + OPB + rb * 64 + dl_swz(rb, lc) * 16);
+  }
+}
+
+template <typename A>
+__device__ __forceinline__ void dl_mfma32(const Frags32& f, A (&acc)[4][4]) {
+#pragma unroll
+  for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < 4; ++fn)
+      acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, f.a[fm]),
+                                                            __builtin_bit_cast(bf16x8, f.b[fn]), acc[fm][fn], 0, 0, 0);
+}
+
 // acc += P[rp0:+BT, k0:k1] * Q[rq0:+BT, k0:k1]^T (bf16), (k1 - k0) % 32 == 0
 template <int BT, typename A>
 __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
@@ -485,16 +529,74 @@ __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
     const int ks = s < nk ? s : nk - 1;
     dl_issue_stage<BT>(pP, pQ, ld, ks * C::BK, smem + s * C::STB, wave, lane);
   }
-  for (int kt = 0; kt < nk; ++kt) {
-    // this wave's loads of stage kt are done once at most NS-2 later stages are pending
-    wait_vmcnt<(C::NS - 2) * C::LPS>();
-    __builtin_amdgcn_s_barrier();  // everyone's loads of stage kt landed; stage kt-1's slot is free
-    {
-      const int ks = kt + C::NS - 1 < nk ? kt + C::NS - 1 : nk - 1;
-      dl_issue_stage<BT>(pP, pQ, ld, ks * C::BK, smem + ((kt + C::NS - 1) % C::NS) * C::STB, wave, lane);
+  if constexpr (BT == 128) {
+    for (int kt = 0; kt < nk; ++kt) {
+      // this wave's loads of stage kt are done once at most NS-2 later stages are pending
+      wait_vmcnt<(C::NS - 2) * C::LPS>();
+      lds_barrier();  // everyone's loads of stage kt landed; stage kt-1's slot is free
+      {
+        const int ks = kt + C::NS - 1 < nk ? kt + C::NS - 1 : nk - 1;
+        dl_issue_stage<BT>(pP, pQ, ld, ks * C::BK, smem + ((kt + C::NS - 1) % C::NS) * C::STB, wave, lane);
+      }
+      const char* cur = smem + (kt % C::NS) * C::STB;
+      dl_mma_stage<BT>(cur, cur + C::OPB, wm, wn, lane, acc);
     }
-    const char* cur = smem + (kt % C::NS) * C::STB;
-    dl_mma_stage<BT>(cur, cur + C::OPB, wm, wn, lane, acc);
+  } else {
+    // 256 tile, two 16-deep k-steps per stage, software-pipelined: the
+    // fragments of the next k-step are read from LDS while the MFMAs of the
+    // current one run, and the stage barrier sits between the two halves, so
+    // neither LDS latency nor the barrier stands between two MFMA groups.
+    // Explicit waits at the end of each half leave nothing in flight at the
+    // loop header, and scheduling fences keep the compiler's scheduler from
+    // re-serialising reads and MFMAs.
+    static_assert(BT == 256, "pipelined loop is written for the 256 tile");
+    wait_vmcnt<(C::NS - 2) * C::LPS>();
+    lds_barrier();  // stage 0 visible
+    Frags32 f0, f1;
+    dl_read_frags32(smem, 0, wm, wn, lane, f0);
+    wait_lgkm0();
+    for (int kt = 0; kt < nk; ++kt) {
+      const char* cur = smem + (kt % C::NS) * C::STB;
+      __builtin_amdgcn_sched_barrier(0);
+      dl_read_frags32(cur, 1, wm, wn, lane, f1);
+      dl_mfma32(f0, acc);
+      // 8 LDS reads spread over the first 8 of 16 MFMAs
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      wait_lgkm0();
+      // own loads of stage kt+1 landed; after the barrier everyone's have, and
+      // every wave has finished reading stage kt-1's slot (its last reads were
+      // waited for before this wave's previous barrier)
+      wait_vmcnt<(C::NS - 3) * C::LPS>();
+      lds_barrier();
+      __builtin_amdgcn_sched_barrier(0);
+      {
+        const int ks = kt + C::NS - 1 < nk ? kt + C::NS - 1 : nk - 1;
+        dl_issue_stage<BT>(pP, pQ, ld, ks * C::BK, smem + ((kt + C::NS - 1) % C::NS) * C::STB, wave, lane);
+      }
+      const int nx = kt + 1 < nk ? kt + 1 : kt;
+      dl_read_frags32(smem + (nx % C::NS) * C::STB, 0, wm, wn, lane, f0);
+      dl_mfma32(f1, acc);
+      // 8 direct-to-LDS loads, then 8 LDS reads, each paired with an MFMA
+#pragma unroll
+      for (int q = 0; q < C::LPS; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x010, 1, 1);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 1);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 1);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 1);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      wait_lgkm0();
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
   wait_vmcnt<0>();  // no LDS write may still be in flight when the ring is reused
 }
