@@ -107,6 +107,26 @@ def spec_norm_gpu(D, torch, iters=60):
     return float(lam.sqrt())
 
 
+def measured_traffic(workload, compute, tile, fp8_steps):
+    """HBM bytes per update launch from the committed counter runs, when they were
+    taken on this workload and on the kernel source as it is now (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload.replace('-', '_')}.json")
+    if compute != "bf16" or tile != 0 or fp8_steps or not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        src = os.path.join(ROOT, "paper_2505_16932_amd", "csrc", "kernels.hip")
+        with open(src, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != t["kernels_hip_sha256"]:
+                return None
+        return dict(gb=round((t["fetch_bytes"] + t["write_bytes"]) / 1e9, 2),
+                    read_gb=round(t["fetch_bytes"] / 1e9, 2), write_gb=round(t["write_bytes"] / 1e9, 2))
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(G_cpu64, abc, T):
     """The FP64 oracle on the host cores, on one matrix of the workload."""
     import numpy as np
@@ -141,6 +161,9 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="0 auto, 1 = 128x128, 2 = 256x256 block tile")
     ap.add_argument("--inputs", default="spectral", choices=["spectral", "gaussian"],
                     help="gaussian: iid inputs of the same shapes (profiler runs; no polar error)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy this many MiB device to device (a kernel of known traffic "
+                         "that scales the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -156,6 +179,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     dev = torch.device("cuda:0")
     pe.lib()
+    if args.copy_probe_mib > 0:
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {nb} bytes read, {nb} bytes written")
+        del src, dst
     log(f"[bench] generating workload {args.workload}")
     t0 = time.perf_counter()
     Gs, T, meta = make_workload(args.workload, torch, dev, args.inputs)
@@ -240,6 +272,7 @@ def main():
         log(f"[bench] cpu oracle {cpu['value']:.4f} TFLOP/s")
 
     peak = PEAK_BF16_TFLOPS
+    traffic = measured_traffic(args.workload, args.compute, args.tile, args.fp8_steps)
     out = {
         "metric": "polar TFLOP/s & % MFMA peak at fixed ||X-UV^T||_2, batched vs plain bf16",
         "value": round(tflops, 3),
@@ -259,7 +292,10 @@ def main():
         "pct_bf16_peak": round(100.0 * tflops / peak, 2),
         "matrices_per_s": round(len(Gs) / (ms * 1e-3), 2),
         "roofline": {"bound": "mfma", "achieved": round(upd_tf, 2), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(upd_tf / peak, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(upd_tf / peak, 4),
+                     "traffic": traffic["gb"] if traffic else None,
+                     "traffic_unit": "GB of HBM traffic per launch (scaled FETCH_SIZE + WRITE_SIZE)",
+                     "traffic_read_write_gb": [traffic["read_gb"], traffic["write_gb"]] if traffic else None,
                      "kernel": "gemm_kernel<bf16, update> (X = aX + BX)",
                      "avg_ms": round(upd_ms, 4)},
         "cpu_baseline": cpu,

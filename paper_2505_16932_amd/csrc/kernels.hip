@@ -636,7 +636,38 @@ __device__ __forceinline__ void tri_decode(int u, int nb, int* ti, int* tj) {
   *tj = r + u;
 }
 
-// inverse of tri_decode
+// Upper-triangle tile (ti <= tj) from a position in banded order: bands of
+// GM tile rows; inside a band, columns left to right, the band's rows (those
+// with ti <= tj) fastest.  Consecutive positions then share column panels and
+// cycle through GM row panels, as in banded_decode, so the tiles that one XCD
+// runs together touch few distinct operand panels.  A band of R rows starting
+// at row r0 holds R(R+1)/2 tiles in its first R columns, then R per column.
+__device__ __forceinline__ void tri_decode_banded(int u, int nb, int* ti, int* tj) {
+  constexpr int GM = 8;
+  int r0 = 0;
+  for (;;) {
+    const int R = min(GM, nb - r0);
+    const int tri = R * (R + 1) / 2;
+    const int cnt = tri + (nb - r0 - R) * R;
+    if (u < cnt) {
+      if (u < tri) {
+        int c = 0;
+        while ((c + 1) * (c + 2) / 2 <= u) ++c;
+        *tj = r0 + c;
+        *ti = r0 + (u - c * (c + 1) / 2);
+      } else {
+        const int v = u - tri;
+        *tj = r0 + R + v / R;
+        *ti = r0 + v % R;
+      }
+      return;
+    }
+    u -= cnt;
+    r0 += R;
+  }
+}
+
+// inverse of tri_decode (row-major index, used for per-tile partial sums)
 __device__ __forceinline__ int tri_index(int ti, int tj, int nb) {
   return ti * nb - (ti * (ti - 1)) / 2 + (tj - ti);
 }
@@ -1026,7 +1057,7 @@ __global__ __launch_bounds__(kThreads, BT == 128 ? 2 : 1) void gemm_kernel(KArgs
       const int split = KIND == KIND_GRAM ? d.gram_split : d.a2_split;
       const int tile = local / split, ksp = local % split;
       int ti, tj;
-      tri_decode(tile, d.nb, &ti, &tj);
+      tri_decode_banded(tile, d.nb, &ti, &tj);
       const T* Op;
       int K;
       if (KIND == KIND_GRAM) {
@@ -1083,7 +1114,7 @@ __global__ __launch_bounds__(kThreads) void splitk_reduce_kernel(KArgs args) {
     const int tile = item - args.offs[mi];
     const int split = KIND == KIND_GRAM ? d.gram_split : d.a2_split;
     int ti, tj;
-    tri_decode(tile, d.nb, &ti, &tj);
+    tri_decode_banded(tile, d.nb, &ti, &tj);
     Acc acc[4][4];
     const float4* part = (const float4*)d.part + ((size_t)tile * split * Q) * kThreads;
 #pragma unroll
