@@ -278,6 +278,21 @@ struct AccT<4> { typedef f32x4 type; };
 template <>
 struct AccT<16> { typedef float type __attribute__((ext_vector_type(16))); };
 
+// Waves of a GEMM block and their grid over the BT x BT tile: two wave rows
+// of BT/2 tile rows each; WGN wave columns of WTN tile columns, each holding
+// FN fragments of F x F.  The bf16 256 tile runs 8 waves (2 per SIMD, wave
+// tile 128 x 64): one wave's LDS reads, barrier waits and epilogue memory
+// latency then overlap the other's MFMAs.  Every other path runs 4 waves.
+template <int P, int BT>
+struct WaveCfg {
+  static constexpr int NW = (P == kBF16 && BT == 256) ? 8 : 4;
+  static constexpr int NT = NW * 64;
+  static constexpr int WGN = NW / 2;
+  static constexpr int F = BT / 8;
+  static constexpr int FN = 8 / WGN;
+  static constexpr int WTN = FN * F;
+};
+
 template <typename T>
 struct OpT;
 template <>
@@ -403,7 +418,8 @@ struct DlCfg {
   static constexpr int OPB = BT * ROWB;          // one operand, one stage
   static constexpr int STB = 2 * OPB;            // one stage
   static constexpr int LDS = NS * STB;
-  static constexpr int IPW = OPB / 1024 / 4;     // 1-KB loads per wave per operand per stage
+  static constexpr int NW = WaveCfg<kBF16, BT>::NW;
+  static constexpr int IPW = OPB / 1024 / NW;    // 1-KB loads per wave per operand per stage
   static constexpr int LPS = 2 * IPW;            // load instructions per wave per stage
 };
 
@@ -480,11 +496,11 @@ __device__ __forceinline__ void dl_mma_stage(const char* sA, const char* sB, int
 // s_waitcnt lgkmcnt(0) with vmcnt and expcnt left at their maxima
 __device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
-// Fragments of one 16-deep k-step of the 256 tile (32x32x16 MFMA): rows
-// lane % 32 of four 32-row fragments per operand, 16-byte chunk
-// 2 * sub + lane / 32 of the stage's 64-byte row.
+// Fragments of one 16-deep k-step of the 256 tile (32x32x16 MFMA, 8 waves):
+// rows lane % 32 of four 32-row fragments of the first operand and two of the
+// second, 16-byte chunk 2 * sub + lane / 32 of the stage's 64-byte row.
 struct Frags32 {
-  u32x4 a[4], b[4];
+  u32x4 a[4], b[2];
 };
 
 __device__ __forceinline__ void dl_read_frags32(const char* stage, int sub, int wm, int wn, int lane,
@@ -494,30 +510,35 @@ __device__ __forceinline__ void dl_read_frags32(const char* stage, int sub, int 
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int ra = wm * 128 + i * 32 + (lane & 31);
-    const int rb = wn * 128 + i * 32 + (lane & 31);
     f.a[i] = *(const u32x4*)(stage + ra * 64 + dl_swz(ra, lc) * 16);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int rb = wn * 64 + i * 32 + (lane & 31);
     f.b[i] = *(const u32x4*)(stage + OPB + rb * 64 + dl_swz(rb, lc) * 16);
   }
 }
 
 template <typename A>
-__device__ __forceinline__ void dl_mfma32(const Frags32& f, A (&acc)[4][4]) {
+__device__ __forceinline__ void dl_mfma32(const Frags32& f, A (&acc)[4][2]) {
 #pragma unroll
   for (int fm = 0; fm < 4; ++fm)
 #pragma unroll
-    for (int fn = 0; fn < 4; ++fn)
+    for (int fn = 0; fn < 2; ++fn)
       acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, f.a[fm]),
                                                             __builtin_bit_cast(bf16x8, f.b[fn]), acc[fm][fn], 0, 0, 0);
 }
 
 // acc += P[rp0:+BT, k0:k1] * Q[rq0:+BT, k0:k1]^T (bf16), (k1 - k0) % 32 == 0
-template <int BT, typename A>
+template <int BT, typename A, int FN>
 __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
                                                 const uint16_t* __restrict__ Q, int64_t ld, int rp0,
-                                                int rq0, int k0, int k1, char* smem, A (&acc)[4][4]) {
+                                                int rq0, int k0, int k1, char* smem, A (&acc)[4][FN]) {
   typedef DlCfg<BT> C;
+  typedef WaveCfg<kBF16, BT> W;
+  static_assert(FN == W::FN, "accumulator grid");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / W::WGN, wn = wave % W::WGN;
   const PE_GLOBAL uint16_t* pP = gview(P) + (size_t)rp0 * ld + k0;
   const PE_GLOBAL uint16_t* pQ = gview(Q) + (size_t)rq0 * ld + k0;
   const int nk = (k1 - k0) / C::BK;
@@ -530,6 +551,7 @@ __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
     dl_issue_stage<BT>(pP, pQ, ld, ks * C::BK, smem + s * C::STB, wave, lane);
   }
   if constexpr (BT == 128) {
+    static_assert(W::NW == 4 && FN == 4, "128 tile: 4 waves");
     for (int kt = 0; kt < nk; ++kt) {
       // this wave's loads of stage kt are done once at most NS-2 later stages are pending
       wait_vmcnt<(C::NS - 2) * C::LPS>();
@@ -549,7 +571,7 @@ __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
     // Explicit waits at the end of each half leave nothing in flight at the
     // loop header, and scheduling fences keep the compiler's scheduler from
     // re-serialising reads and MFMAs.
-    static_assert(BT == 256, "pipelined loop is written for the 256 tile");
+    static_assert(BT == 256 && W::NW == 8, "pipelined loop is written for the 8-wave 256 tile");
     wait_vmcnt<(C::NS - 2) * C::LPS>();
     lds_barrier();  // stage 0 visible
     Frags32 f0, f1;
@@ -560,13 +582,13 @@ __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
       __builtin_amdgcn_sched_barrier(0);
       dl_read_frags32(cur, 1, wm, wn, lane, f1);
       dl_mfma32(f0, acc);
-      // 8 LDS reads spread over the first 8 of 16 MFMAs
+      // 6 LDS reads spread over the first 6 of 8 MFMAs
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < 6; ++q) {
         __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
       }
-      __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
       __builtin_amdgcn_sched_barrier(0);
       wait_lgkm0();
       // own loads of stage kt+1 landed; after the barrier everyone's have, and
@@ -582,17 +604,20 @@ __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
       const int nx = kt + 1 < nk ? kt + 1 : kt;
       dl_read_frags32(smem + (nx % C::NS) * C::STB, 0, wm, wn, lane, f0);
       dl_mfma32(f1, acc);
-      // 8 direct-to-LDS loads, then 8 LDS reads, each paired with an MFMA
+      // 4 direct-to-LDS loads and 6 LDS reads spread over the first 6 of 8 MFMAs
+      static_assert(C::LPS == 4, "load count per stage");
 #pragma unroll
-      for (int q = 0; q < C::LPS; ++q) {
+      for (int q = 0; q < 4; ++q) {
         __builtin_amdgcn_sched_group_barrier(0x010, 1, 1);
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 1);
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
         __builtin_amdgcn_sched_group_barrier(0x100, 1, 1);
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 1);
       }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 1);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 1);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 2, 1);
       __builtin_amdgcn_sched_barrier(0);
       wait_lgkm0();
       __builtin_amdgcn_sched_barrier(0);
@@ -833,18 +858,19 @@ __device__ __forceinline__ float fp8_operand_scale(const MatDesc& d, int kind, i
 // ------------------------------------------------------------- epilogues
 // Accumulator element (fm, fn, g, r) is C[row][col] of the block tile with
 //   F = 16: row = wm*BT/2 + fm*16 + 4*(lane/16) + r,           col = wn*BT/2 + fn*16 + lane%16
-//   F = 32: row = wm*BT/2 + fm*32 + 8*g + 4*(lane/32) + r,     col = wn*BT/2 + fn*32 + lane%32
-// with acc register index 4*g + r; each (fm, fn, g) is four consecutive rows.
+//   F = 32: row = wm*BT/2 + fm*32 + 8*g + 4*(lane/32) + r,     col = wn*WTN + fn*32 + lane%32
+// with acc register index 4*g + r (WTN = BT/2 with 4 waves, BT/4 with 8); each
+// (fm, fn, g) is four consecutive rows.
 template <int BT>
 __device__ __forceinline__ int acc_row(int wm, int fm, int g, int lane) {
   constexpr int F = TileCfg<BT>::F;
   return F == 16 ? wm * (BT / 2) + fm * 16 + 4 * (lane >> 4)
                  : wm * (BT / 2) + fm * 32 + 8 * g + 4 * (lane >> 5);
 }
-template <int BT>
+template <int P, int BT>
 __device__ __forceinline__ int acc_col(int wn, int fn, int lane) {
   constexpr int F = TileCfg<BT>::F;
-  return wn * (BT / 2) + fn * F + (lane % F);
+  return wn * WaveCfg<P, BT>::WTN + fn * F + (lane % F);
 }
 
 // The epilogues read one FP32 matrix (A for B = bA + cA^2, X for X = aX + BX)
@@ -852,31 +878,37 @@ __device__ __forceinline__ int acc_col(int wn, int fn, int lane) {
 // A lane's inputs of one fragment row fm (4 fragments) are loaded before the
 // stores of the previous row are issued, so the loads of a row overlap instead
 // of each one waiting behind the stores the compiler must keep ahead of it.
-template <int BT>
+template <int P, int BT>
 struct FragRow {
-  float x[4][TileCfg<BT>::RG][4];  // [fn][row group][r]
+  float x[WaveCfg<P, BT>::FN][TileCfg<BT>::RG][4];  // [fn][row group][r]
 };
 
-template <int BT>
+template <int P, int BT>
 __device__ __forceinline__ void load_frag_row(const float* __restrict__ src, size_t ld, int row0,
                                               int col0, int wm, int wn, int fm, int lane,
-                                              FragRow<BT>& f) {
+                                              FragRow<P, BT>& f) {
 #pragma unroll
-  for (int fn = 0; fn < 4; ++fn)
+  for (int fn = 0; fn < WaveCfg<P, BT>::FN; ++fn)
 #pragma unroll
     for (int g = 0; g < TileCfg<BT>::RG; ++g) {
-      const size_t o = (size_t)(row0 + acc_row<BT>(wm, fm, g, lane)) * ld + col0 + acc_col<BT>(wn, fn, lane);
+      const size_t o = (size_t)(row0 + acc_row<BT>(wm, fm, g, lane)) * ld + col0 + acc_col<P, BT>(wn, fn, lane);
 #pragma unroll
       for (int r = 0; r < 4; ++r) f.x[fn][g][r] = src[o + (size_t)r * ld];
     }
 }
 
-template <int P, int BT, typename A>
+// red: LDS scratch of at least 4 * NW doubles for the moment reduction (the
+// GEMM kernel lends its operand ring, free once the main loop is done; a
+// kernel with a single LDS object keeps the compiler's LDS-DMA wait tracking
+// from turning into a full vmcnt(0) wait after every stage's loads).
+template <int P, int BT, typename A, int FN>
 __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, int kind, int ti,
-                                         int tj, float deq, const A (&acc)[4][4]) {
+                                         int tj, float deq, const A (&acc)[4][FN], double* red) {
   typedef TileCfg<BT> C;
+  typedef WaveCfg<P, BT> W;
+  static_assert(FN == W::FN, "accumulator grid");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / W::WGN, wn = wave % W::WGN;
   const size_t sp = d.sp;
   // only B = bA + cA^2 needs the step's coefficients
   float a = 0.0f, b = 0.0f, c = 0.0f;
@@ -890,18 +922,18 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
   float amax = 0.0f;
   double mom[4] = {0.0, 0.0, 0.0, 0.0};
   const bool reads_a = kind == KIND_A2;
-  FragRow<BT> pre[2];
-  if (reads_a) load_frag_row<BT>(d.Af, sp, ti * BT, tj * BT, wm, wn, 0, lane, pre[0]);
+  FragRow<P, BT> pre[2];
+  if (reads_a) load_frag_row<P, BT>(d.Af, sp, ti * BT, tj * BT, wm, wn, 0, lane, pre[0]);
 #pragma unroll
   for (int fm = 0; fm < 4; ++fm) {
-    if (reads_a && fm + 1 < 4) load_frag_row<BT>(d.Af, sp, ti * BT, tj * BT, wm, wn, fm + 1, lane, pre[(fm + 1) & 1]);
-    const FragRow<BT>& cur = pre[fm & 1];
+    if (reads_a && fm + 1 < 4) load_frag_row<P, BT>(d.Af, sp, ti * BT, tj * BT, wm, wn, fm + 1, lane, pre[(fm + 1) & 1]);
+    const FragRow<P, BT>& cur = pre[fm & 1];
 #pragma unroll
-    for (int fn = 0; fn < 4; ++fn) {
+    for (int fn = 0; fn < FN; ++fn) {
 #pragma unroll
       for (int g = 0; g < C::RG; ++g) {
         const int i = ti * BT + acc_row<BT>(wm, fm, g, lane);
-        const int j = tj * BT + acc_col<BT>(wn, fn, lane);
+        const int j = tj * BT + acc_col<P, BT>(wn, fn, lane);
         float v[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -950,7 +982,6 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
   if (kind == KIND_GRAM && args.fp8) wave_amax_atomic(amax, d.scal + kScAmaxA + args.t);
   if (kind == KIND_A2 && args.raw_a2) {
     // fixed-order block reduction of the tile's moment partials
-    __shared__ double red[4][kThreads / 64];
     const int tileid = tri_index(ti, tj, d.nb);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -960,39 +991,44 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
     }
     __syncthreads();
     if (lane == 0)
-      for (int k = 0; k < 4; ++k) red[k][wave] = mom[k];
+      for (int k = 0; k < 4; ++k) red[k * W::NW + wave] = mom[k];
     __syncthreads();
     if (threadIdx.x < 4) {
       const int k = threadIdx.x;
-      d.mom[(size_t)tileid * 4 + k] = (red[k][0] + red[k][1]) + (red[k][2] + red[k][3]);
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < W::NW; ++w) t += red[k * W::NW + w];
+      d.mom[(size_t)tileid * 4 + k] = t;
     }
   }
 }
 
-template <int P, int BT, bool LAST, typename A>
+template <int P, int BT, bool LAST, typename A, int FN>
 __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, int tm, int tn,
-                                           const A (&acc)[4][4]) {
+                                           const A (&acc)[4][FN]) {
   typedef TileCfg<BT> C;
+  typedef WaveCfg<P, BT> W;
+  static_assert(FN == W::FN, "accumulator grid");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / W::WGN, wn = wave % W::WGN;
   float a, b, c;
   step_coef(args, d, &a, &b, &c);
   const float alpha = (args.t == 0) ? d.scal[kScScale] : 1.0f;
   const size_t Lp = d.Lp, sp = d.sp;
   void* XTn = (args.t & 1) ? d.XT0 : d.XT1;
   float amax = 0.0f;
-  FragRow<BT> pre[2];
-  load_frag_row<BT>(d.Xf, Lp, tm * BT, tn * BT, wm, wn, 0, lane, pre[0]);
+  FragRow<P, BT> pre[2];
+  load_frag_row<P, BT>(d.Xf, Lp, tm * BT, tn * BT, wm, wn, 0, lane, pre[0]);
 #pragma unroll
   for (int fm = 0; fm < 4; ++fm) {
-    if (fm + 1 < 4) load_frag_row<BT>(d.Xf, Lp, tm * BT, tn * BT, wm, wn, fm + 1, lane, pre[(fm + 1) & 1]);
-    const FragRow<BT>& cur = pre[fm & 1];
+    if (fm + 1 < 4) load_frag_row<P, BT>(d.Xf, Lp, tm * BT, tn * BT, wm, wn, fm + 1, lane, pre[(fm + 1) & 1]);
+    const FragRow<P, BT>& cur = pre[fm & 1];
 #pragma unroll
-    for (int fn = 0; fn < 4; ++fn) {
+    for (int fn = 0; fn < FN; ++fn) {
 #pragma unroll
       for (int g = 0; g < C::RG; ++g) {
         const int i = tm * BT + acc_row<BT>(wm, fm, g, lane);
-        const int n = tn * BT + acc_col<BT>(wn, fn, lane);
+        const int n = tn * BT + acc_col<P, BT>(wn, fn, lane);
         float v[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[r] = alpha * (a * cur.x[fn][g][r] + acc[fm][fn][4 * g + r]);
@@ -1025,9 +1061,10 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
 
 // ------------------------------------------------------------- kernels
 template <int P, int KIND, int BT>
-__global__ __launch_bounds__(kThreads, BT == 128 ? 2 : 1) void gemm_kernel(KArgs args) {
+__global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gemm_kernel(KArgs args) {
   using T = typename std::conditional<P == kF32, float, uint16_t>::type;
   typedef TileCfg<BT> C;
+  typedef WaveCfg<P, BT> W;
   typedef typename AccT<C::ACC>::type Acc;
   constexpr int BK = P == kFP8 ? Fp8Cfg<BT>::KQ : (P == kBF16 ? DlCfg<BT>::BK : OpT<T>::kBK);
   constexpr int LDSB = P == kFP8 ? Fp8Cfg<BT>::LDS : (P == kBF16 ? DlCfg<BT>::LDS : C::LDS);
@@ -1038,11 +1075,11 @@ __global__ __launch_bounds__(kThreads, BT == 128 ? 2 : 1) void gemm_kernel(KArgs
     const MatDesc& d = args.descs[mi];
     if (skip_matrix(args, d)) continue;
     const int local = item - args.offs[mi];
-    Acc acc[4][4];
+    Acc acc[4][W::FN];
 #pragma unroll
     for (int fm = 0; fm < 4; ++fm)
 #pragma unroll
-      for (int fn = 0; fn < 4; ++fn) acc[fm][fn] = Acc{};
+      for (int fn = 0; fn < W::FN; ++fn) acc[fm][fn] = Acc{};
     if constexpr (KIND == KIND_UPD || KIND == KIND_UPD_LAST) {
       int tm, tn;
       banded_decode(local, d.nb, d.nbL, &tm, &tn);
@@ -1081,19 +1118,19 @@ __global__ __launch_bounds__(kThreads, BT == 128 ? 2 : 1) void gemm_kernel(KArgs
         if (k1 > k0) gemm_nt_tile<T, BT>(Op, Op, K, ti * BT, tj * BT, k0, k1, smem, acc);
       }
       if (split == 1) {
-        epi_syrk<P, BT>(args, d, KIND, ti, tj, deq, acc);
+        epi_syrk<P, BT>(args, d, KIND, ti, tj, deq, acc, (double*)smem);
       } else {
-        // partial tile: float4 q of thread t at ((tile*split + ksp)*Q + q)*256 + t
-        constexpr int Q = 16 * C::ACC / 4;
-        float4* part = (float4*)d.part + ((size_t)(tile * split + ksp) * Q) * kThreads;
+        // partial tile: float4 q of thread t at ((tile*split + ksp)*Q + q)*NT + t
+        constexpr int Q = 4 * W::FN * C::ACC / 4;
+        float4* part = (float4*)d.part + ((size_t)(tile * split + ksp) * Q) * W::NT;
 #pragma unroll
         for (int fm = 0; fm < 4; ++fm)
 #pragma unroll
-          for (int fn = 0; fn < 4; ++fn)
+          for (int fn = 0; fn < W::FN; ++fn)
 #pragma unroll
             for (int g = 0; g < C::ACC / 4; ++g) {
-              const int q = (fm * 4 + fn) * (C::ACC / 4) + g;
-              part[q * kThreads + threadIdx.x] =
+              const int q = (fm * W::FN + fn) * (C::ACC / 4) + g;
+              part[q * W::NT + threadIdx.x] =
                   make_float4(acc[fm][fn][4 * g], acc[fm][fn][4 * g + 1], acc[fm][fn][4 * g + 2],
                               acc[fm][fn][4 * g + 3]);
             }
@@ -1103,10 +1140,12 @@ __global__ __launch_bounds__(kThreads, BT == 128 ? 2 : 1) void gemm_kernel(KArgs
 }
 
 template <int P, int KIND, int BT>
-__global__ __launch_bounds__(kThreads) void splitk_reduce_kernel(KArgs args) {
+__global__ __launch_bounds__((WaveCfg<P, BT>::NT)) void splitk_reduce_kernel(KArgs args) {
   typedef TileCfg<BT> C;
+  typedef WaveCfg<P, BT> W;
   typedef typename AccT<C::ACC>::type Acc;
-  constexpr int Q = 16 * C::ACC / 4;
+  constexpr int Q = 4 * W::FN * C::ACC / 4;
+  __shared__ double red[4 * W::NW];
   for (int item = blockIdx.x; item < args.total; item += gridDim.x) {
     const int mi = find_mat(args.offs, args.count, item);
     const MatDesc& d = args.descs[mi];
@@ -1115,18 +1154,18 @@ __global__ __launch_bounds__(kThreads) void splitk_reduce_kernel(KArgs args) {
     const int split = KIND == KIND_GRAM ? d.gram_split : d.a2_split;
     int ti, tj;
     tri_decode_banded(tile, d.nb, &ti, &tj);
-    Acc acc[4][4];
-    const float4* part = (const float4*)d.part + ((size_t)tile * split * Q) * kThreads;
+    Acc acc[4][W::FN];
+    const float4* part = (const float4*)d.part + ((size_t)tile * split * Q) * W::NT;
 #pragma unroll
     for (int fm = 0; fm < 4; ++fm)
 #pragma unroll
-      for (int fn = 0; fn < 4; ++fn)
+      for (int fn = 0; fn < W::FN; ++fn)
 #pragma unroll
         for (int g = 0; g < C::ACC / 4; ++g) {
-          const int q = (fm * 4 + fn) * (C::ACC / 4) + g;
-          float4 s = part[q * kThreads + threadIdx.x];
+          const int q = (fm * W::FN + fn) * (C::ACC / 4) + g;
+          float4 s = part[q * W::NT + threadIdx.x];
           for (int k = 1; k < split; ++k) {
-            const float4 p = part[((size_t)k * Q + q) * kThreads + threadIdx.x];
+            const float4 p = part[((size_t)k * Q + q) * W::NT + threadIdx.x];
             s.x += p.x; s.y += p.y; s.z += p.z; s.w += p.w;
           }
           acc[fm][fn][4 * g] = s.x;
@@ -1139,7 +1178,7 @@ __global__ __launch_bounds__(kThreads) void splitk_reduce_kernel(KArgs args) {
       const float q = fp8_operand_scale(d, KIND, args.t);
       deq = 1.0f / (q * q);
     }
-    epi_syrk<P, BT>(args, d, KIND, ti, tj, deq, acc);
+    epi_syrk<P, BT>(args, d, KIND, ti, tj, deq, acc, red);
   }
 }
 
@@ -1180,21 +1219,21 @@ hipError_t launch_prep(int prec, const KArgs& a, int grid_cap, hipStream_t st) {
 template <int P, int BT>
 static void launch_gemm_t(int kind, const KArgs& a, int g, hipStream_t st) {
   if (kind == KIND_GRAM)
-    hipLaunchKernelGGL((gemm_kernel<P, KIND_GRAM, BT>), dim3(g), dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL((gemm_kernel<P, KIND_GRAM, BT>), dim3(g), dim3(WaveCfg<P, BT>::NT), 0, st, a);
   else if (kind == KIND_A2)
-    hipLaunchKernelGGL((gemm_kernel<P, KIND_A2, BT>), dim3(g), dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL((gemm_kernel<P, KIND_A2, BT>), dim3(g), dim3(WaveCfg<P, BT>::NT), 0, st, a);
   else if (!a.last)
-    hipLaunchKernelGGL((gemm_kernel<P, KIND_UPD, BT>), dim3(g), dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL((gemm_kernel<P, KIND_UPD, BT>), dim3(g), dim3(WaveCfg<P, BT>::NT), 0, st, a);
   else
-    hipLaunchKernelGGL((gemm_kernel<P, KIND_UPD_LAST, BT>), dim3(g), dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL((gemm_kernel<P, KIND_UPD_LAST, BT>), dim3(g), dim3(WaveCfg<P, BT>::NT), 0, st, a);
 }
 
 template <int P, int BT>
 static void launch_reduce_t(int kind, const KArgs& a, int g, hipStream_t st) {
   if (kind == KIND_GRAM)
-    hipLaunchKernelGGL((splitk_reduce_kernel<P, KIND_GRAM, BT>), dim3(g), dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL((splitk_reduce_kernel<P, KIND_GRAM, BT>), dim3(g), dim3(WaveCfg<P, BT>::NT), 0, st, a);
   else
-    hipLaunchKernelGGL((splitk_reduce_kernel<P, KIND_A2, BT>), dim3(g), dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL((splitk_reduce_kernel<P, KIND_A2, BT>), dim3(g), dim3(WaveCfg<P, BT>::NT), 0, st, a);
 }
 
 hipError_t launch_gemm(int prec, int bt, int kind, const KArgs& a, int grid_cap, hipStream_t st) {
