@@ -73,8 +73,8 @@ def iteration_bf16_operands(G, abc):
     after rounding, so step 1 takes the operand bf16(G) and
         A_1 = sigma^2 bf16(G) bf16(G)^T,  X_1 = sigma (a G + bf16(B_1) bf16(G));
     later steps take bf16(X) for the Gram product and the update, bf16(A) for
-    A^2 and bf16(B) for the update, while the a X term uses the unrounded
-    iterate (the FP32 master).  The distance of this model from the FP64
+    A^2 and for the b A term of B, and bf16(B) for the update, while the a X
+    term uses the unrounded iterate (the FP32 master).  The distance of this model from the FP64
     iteration is the part of the error that bf16 operands cause at all; it sets
     a per-input tolerance where the 3e-2 bar is out of reach of the arithmetic."""
     G = np.asarray(G, dtype=np.float64)
@@ -88,6 +88,6 @@ def iteration_bf16_operands(G, abc):
         Xo = round_bf16(X.astype(np.float32))
         A = scale * scale * (Xo @ Xo.T)
         Ao = round_bf16(A.astype(np.float32))
-        B = b * A + c * (Ao @ Ao)
+        B = b * Ao + c * (Ao @ Ao)
         X = scale * (a * X + round_bf16(B.astype(np.float32)) @ Xo)
     return X.T if tall else X

@@ -883,8 +883,15 @@ struct FragRow {
   float x[WaveCfg<P, BT>::FN][TileCfg<BT>::RG][4];  // [fn][row group][r]
 };
 
-template <int P, int BT>
-__device__ __forceinline__ void load_frag_row(const float* __restrict__ src, size_t ld, int row0,
+template <typename S>
+__device__ __forceinline__ float load_as_float(const S* p) {
+  if constexpr (sizeof(S) == 2) return bf2f(*p);
+  else return *p;
+}
+
+// S = float or uint16_t (bf16)
+template <int P, int BT, typename S>
+__device__ __forceinline__ void load_frag_row(const S* __restrict__ src, size_t ld, int row0,
                                               int col0, int wm, int wn, int fm, int lane,
                                               FragRow<P, BT>& f) {
 #pragma unroll
@@ -893,7 +900,7 @@ __device__ __forceinline__ void load_frag_row(const float* __restrict__ src, siz
     for (int g = 0; g < TileCfg<BT>::RG; ++g) {
       const size_t o = (size_t)(row0 + acc_row<BT>(wm, fm, g, lane)) * ld + col0 + acc_col<P, BT>(wn, fn, lane);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) f.x[fn][g][r] = src[o + (size_t)r * ld];
+      for (int r = 0; r < 4; ++r) f.x[fn][g][r] = load_as_float(src + o + (size_t)r * ld);
     }
 }
 
@@ -921,12 +928,15 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
   const float calpha = c * deq;
   float amax = 0.0f;
   double mom[4] = {0.0, 0.0, 0.0, 0.0};
+  // the A^2 kinds read A: FP32 on the fp32 path, its bf16 copy otherwise
   const bool reads_a = kind == KIND_A2;
+  typedef typename std::conditional<P == kF32, float, uint16_t>::type AT;
+  const AT* Asrc = P == kF32 ? (const AT*)d.Af : (const AT*)d.As;
   FragRow<P, BT> pre[2];
-  if (reads_a) load_frag_row<P, BT>(d.Af, sp, ti * BT, tj * BT, wm, wn, 0, lane, pre[0]);
+  if (reads_a) load_frag_row<P, BT>(Asrc, sp, ti * BT, tj * BT, wm, wn, 0, lane, pre[0]);
 #pragma unroll
   for (int fm = 0; fm < 4; ++fm) {
-    if (reads_a && fm + 1 < 4) load_frag_row<P, BT>(d.Af, sp, ti * BT, tj * BT, wm, wn, fm + 1, lane, pre[(fm + 1) & 1]);
+    if (reads_a && fm + 1 < 4) load_frag_row<P, BT>(Asrc, sp, ti * BT, tj * BT, wm, wn, fm + 1, lane, pre[(fm + 1) & 1]);
     const FragRow<P, BT>& cur = pre[fm & 1];
 #pragma unroll
     for (int fn = 0; fn < FN; ++fn) {
@@ -941,8 +951,8 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
           const float x = acc[fm][fn][4 * g + r];
           if (kind == KIND_GRAM) {
             v[r] = alpha * x;
-            d.Af[o] = v[r];
-            if (P != kF32) ((uint16_t*)d.As)[o] = f2bf(v[r]);
+            if (P == kF32) d.Af[o] = v[r];
+            else ((uint16_t*)d.As)[o] = f2bf(v[r]);
             amax = fmaxf(amax, fabsf(v[r]));
           } else if (args.raw_a2) {
             // learned path, step 1: keep A^2 and accumulate tr(A^k) partials;
@@ -957,7 +967,8 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
             mom[2] += w * (double)av * (double)a2;
             mom[3] += w * (double)a2 * (double)a2;
           } else {
-            v[r] = b * cur.x[fn][g][r] + calpha * x;
+            // same operation order as the learned path's combine kernel
+            v[r] = __builtin_fmaf(calpha, x, b * cur.x[fn][g][r]);
             if (P == kF32) ((float*)d.Bs)[o] = v[r];
             else ((uint16_t*)d.Bs)[o] = f2bf(v[r]);
           }
@@ -968,8 +979,8 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
           // mirrored tile: row j, columns i..i+3 (contiguous)
           const size_t o = (size_t)j * sp + i;
           if (kind == KIND_GRAM) {
-            *(float4*)(d.Af + o) = make_float4(v[0], v[1], v[2], v[3]);
-            if (P != kF32) *(uint2*)((uint16_t*)d.As + o) = pack4_bf16(v);
+            if (P == kF32) *(float4*)(d.Af + o) = make_float4(v[0], v[1], v[2], v[3]);
+            else *(uint2*)((uint16_t*)d.As + o) = pack4_bf16(v);
           } else {
             if (P == kF32) *(float4*)((float*)d.Bs + o) = make_float4(v[0], v[1], v[2], v[3]);
             else *(uint2*)((uint16_t*)d.Bs + o) = pack4_bf16(v);

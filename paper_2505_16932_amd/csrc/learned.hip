@@ -264,7 +264,10 @@ __global__ __launch_bounds__(256) void combine_kernel(KArgs args) {
     const float b = cf[1], c = cf[2];
     const size_t base = (size_t)row * d.sp;
     for (int j = threadIdx.x; j < d.sp; j += blockDim.x) {
-      const float v = b * d.Af[base + j] + c * d.A2f[base + j];
+      const float av = P == kF32 ? d.Af[base + j]
+                                 : __uint_as_float((uint32_t)((const uint16_t*)d.As)[base + j] << 16);
+      // same operation order as the fused A^2 epilogue (there c * deq, deq = 1)
+      const float v = __builtin_fmaf(c, d.A2f[base + j], b * av);
       if (P == kF32) ((float*)d.Bs)[base + j] = v;
       else {
         uint32_t u = __float_as_uint(v);

@@ -10,8 +10,9 @@
 //   Xf      sp x Lp  fp32   master iterate (row-major)
 //   Xb      sp x Lp  bf16   operand copy of X for the Gram product (bf16/fp8 paths)
 //   XT[2]   Lp x sp  bf16 or fp32   X^T operand for B X (ping-pong across steps)
-//   Af      sp x sp  fp32   A = X X^T
-//   As      sp x sp  bf16   operand copy of A (fp32 path: Af itself)
+//   Af      sp x sp  fp32   A = X X^T (fp32 path only)
+//   As      sp x sp  bf16   A in bf16 on the bf16/fp8 paths, read by A^2 and by
+//                           the bA term of B (fp32 path: Af itself)
 //   Bs      sp x sp  bf16 or fp32   B = bA + cA^2
 //   part    split-K partial tiles of the Gram-side products
 //   red     per-tile partial sums of squares (fp64) and maxima (fp32) of G

@@ -248,7 +248,9 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
       d.Xb = prec == kF32 ? nullptr : take(X * 2);
       d.XT0 = take(X * esz);
       d.XT1 = take(X * esz);
-      d.Af = (float*)take(A * 4);
+      // A in FP32 on the fp32 path; the bf16 paths keep only its bf16 copy,
+      // which both A^2 and the bA term of the combine read
+      d.Af = prec == kF32 ? (float*)take(A * 4) : nullptr;
       d.As = prec == kF32 ? (void*)d.Af : take(A * 2);
       d.Bs = take(A * esz);
       const int split = std::max(d.gram_split, d.a2_split);

@@ -137,6 +137,40 @@ def test_selection_in_plan_matches_oracle(pe, trained):
     plan.close()
 
 
+def test_learned_plan_large_tile_split_k(pe):
+    """The learned path on the 256 tile (8 waves): a 256 x 1024 matrix keeps the
+    raw A^2 epilogue and its moment reduction in the GEMM kernel (no split), a
+    512 x 1024 and a 768 x 1536 matrix take split-K and the reduce kernel.
+    Results equal the plain calls with the forced class's schedule; features
+    agree with the oracle's features of the normalised spectrum."""
+    import torch
+    cases = [(256, 1024, synth.spectrum_powerlaw(256, 1.0)), (512, 1024, np.geomspace(1, 1e-3, 512)),
+             (768, 1536, synth.spectrum_powerlaw(768, 0.7))]
+    Gs, vals = [], []
+    for k, (m, n, sig) in enumerate(cases):
+        g, v = _materialise(30 + k, m, n, sig)
+        Gs.append(g)
+        vals.append(v)
+    abc4 = OS.greedy_schedule(1e-3, 5).abc
+    plan = pe.Plan(Gs, T=5, abc=abc4, compute="bf16", force_class=3, tile=2, out_dtype=torch.float32,
+                   ws_fill=0x5A)
+    plan.launch(graph=False)
+    torch.cuda.synchronize()
+    cls, feats, _, flags = plan.selection()
+    assert cls.tolist() == [3, 3, 3] and flags.tolist() == [0, 0, 0]
+    abc3 = pe.coeffs(OM.CLASS_ELL[3], 5).abc
+    for k, v in enumerate(vals):
+        Y = pe.polar(Gs[k], T=5, abc=abc3, compute="bf16", tile=2, out_dtype=torch.float32)
+        torch.cuda.synchronize()
+        assert relf(to_np(plan.outs[k]), to_np(Y)) <= 1e-6
+        s_hat = np.linalg.svd(v / (1.01 * np.linalg.norm(v) + 1e-7), compute_uv=False)
+        f_ref = OM.features(min(v.shape), max(v.shape), OM.moments_from_spectrum(s_hat))
+        err = np.abs(feats[k] - f_ref).max()
+        print(f"[learned] tile 256 case {k}: max feature err {err:.2e}", flush=True)
+        assert err <= 2e-2
+    plan.close()
+
+
 @pytest.mark.parametrize("fill", [0x00, 0x3F, 0xFF])
 def test_learned_plan_ignores_workspace_contents(pe, fill):
     """The workspace needs no initialisation: whatever it held before (here
