@@ -34,6 +34,8 @@ namespace pe {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 enum Kind : int { KIND_GRAM = 0, KIND_A2 = 1, KIND_UPD = 2, KIND_UPD_LAST = 3 };
@@ -282,10 +284,11 @@ struct AccT<16> { typedef float type __attribute__((ext_vector_type(16))); };
 // of BT/2 tile rows each; WGN wave columns of WTN tile columns, each holding
 // FN fragments of F x F.  The bf16 256 tile runs 8 waves (2 per SIMD, wave
 // tile 128 x 64): one wave's LDS reads, barrier waits and epilogue memory
-// latency then overlap the other's MFMAs.  Every other path runs 4 waves.
+// latency then overlap the other's MFMAs.  The FP8 256 tile uses the same
+// layout; every other path runs 4 waves.
 template <int P, int BT>
 struct WaveCfg {
-  static constexpr int NW = (P == kBF16 && BT == 256) ? 8 : 4;
+  static constexpr int NW = ((P == kBF16 || P == kFP8) && BT == 256) ? 8 : 4;
   static constexpr int NT = NW * 64;
   static constexpr int WGN = NW / 2;
   static constexpr int F = BT / 8;
@@ -845,6 +848,87 @@ __device__ __forceinline__ void gemm_nt_tile_fp8(const uint16_t* __restrict__ P,
   }
 }
 
+// ---------------------------------------- FP8 Gram-side main loop, 256 tile
+// The bf16 operand goes from HBM into the same LDS ring as on the bf16 path;
+// each lane converts the fragment it reads to e4m3 in registers and the block
+// runs v_mfma_scale_f32_32x32x64_f8f6f4 (FP32 accumulation).  One such MFMA
+// takes 64 k per row: lane l holds row l % 32 and k = 32 (l / 32) + 0..31,
+// i.e. one whole 32-k stage row, so stages are consumed in pairs (lanes 0-31
+// read the pair's first stage, lanes 32-63 its second).  The conversion
+// (v_cvt_scalef32_pk_fp8_bf16: e4m3(x / scale), round to nearest even, two
+// values per instruction) takes scale = 1/q, a power of two, so it yields
+// e4m3(q x) exactly as the quantiser does.
+__device__ __forceinline__ int cvt4_e4m3(uint32_t u0, uint32_t u1, float inv_q) {
+  i16x2 r = {0, 0};
+  r = __builtin_amdgcn_cvt_scalef32_pk_fp8_bf16(r, __builtin_bit_cast(bf16x2, u0), inv_q, false);
+  r = __builtin_amdgcn_cvt_scalef32_pk_fp8_bf16(r, __builtin_bit_cast(bf16x2, u1), inv_q, true);
+  return __builtin_bit_cast(int, r);
+}
+
+// one lane's 32 k of `row` of an operand stage (64-byte swizzled rows) as e4m3
+__device__ __forceinline__ i32x8 dl_row_e4m3(const char* op, int row, float inv_q) {
+  const char* r = op + row * 64;
+  i32x8 out;
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch) {
+    const u32x4 c = *(const u32x4*)(r + dl_swz(row, ch) * 16);
+    out[2 * ch] = cvt4_e4m3(c[0], c[1], inv_q);
+    out[2 * ch + 1] = cvt4_e4m3(c[2], c[3], inv_q);
+  }
+  return out;
+}
+
+// acc += q(P)[rp0:+256, k0:k1] * q(Q)[rq0:+256, k0:k1]^T from bf16 operands in
+// HBM quantised to e4m3 with scales qp, qq; (k1 - k0) % 64 == 0.  The ring
+// holds two pairs: pair j+1 loads while pair j is converted and multiplied.
+// Each fragment is converted just before its MFMAs (an FP8 fragment is twice
+// the registers of a bf16 one, and 128 accumulators leave no room for a
+// second set); the other wave on the SIMD covers the LDS latency.
+template <typename A>
+__device__ __forceinline__ void gemm_nt_tile_dl_fp8(const uint16_t* __restrict__ P,
+                                                    const uint16_t* __restrict__ Q, int64_t ld,
+                                                    int rp0, int rq0, int k0, int k1, float qp,
+                                                    float qq, char* smem, A (&acc)[4][2]) {
+  typedef DlCfg<256> C;
+  typedef WaveCfg<kFP8, 256> W;
+  static_assert(W::NW == 8 && C::NS == 4 && C::LPS == 4, "pair ring of the 8-wave 256 tile");
+  constexpr int OPB = C::OPB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / W::WGN, wn = wave % W::WGN;
+  const PE_GLOBAL uint16_t* pP = gview(P) + (size_t)rp0 * ld + k0;
+  const PE_GLOBAL uint16_t* pQ = gview(Q) + (size_t)rq0 * ld + k0;
+  const float inv_qp = 1.0f / qp, inv_qq = 1.0f / qq;
+  const int nk = (k1 - k0) / C::BK;  // even
+  const int np = nk >> 1;
+  auto slot = [&](int s) { return smem + (s & 3) * C::STB; };
+  auto issue = [&](int s) {
+    const int ks = s < nk ? s : nk - 1;
+    dl_issue_stage<256>(pP, pQ, ld, ks * C::BK, slot(s), wave, lane);
+  };
+  __syncthreads();  // the previous tile's readers are done with the ring
+  issue(0);
+  issue(1);
+  for (int j = 0; j < np; ++j) {
+    // own loads of pair j done; after the barrier everyone's are, and every
+    // wave has finished reading pair j-1, whose slots take pair j+1
+    wait_vmcnt<0>();
+    lds_barrier();
+    issue(2 * j + 2);
+    issue(2 * j + 3);
+    const char* st = (lane < 32) ? slot(2 * j) : slot(2 * j + 1);
+    i32x8 b0 = dl_row_e4m3(st + OPB, wn * 64 + (lane & 31), inv_qq);
+    i32x8 b1 = dl_row_e4m3(st + OPB, wn * 64 + 32 + (lane & 31), inv_qq);
+#pragma unroll
+    for (int fm = 0; fm < 4; ++fm) {
+      const i32x8 a = dl_row_e4m3(st, wm * 128 + fm * 32 + (lane & 31), inv_qp);
+      // format 0 = e4m3 for both operands, E8M0 block scales 127 = 1.0
+      acc[fm][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, acc[fm][0], 0, 0, 0, 127, 0, 127);
+      acc[fm][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, acc[fm][1], 0, 0, 0, 127, 0, 127);
+    }
+  }
+  wait_vmcnt<0>();  // no LDS write may still be in flight when the ring is reused
+}
+
 // Scale of step t's Gram-side operand (kind GRAM: X_t, kind A2: A_t).
 __device__ __forceinline__ float fp8_operand_scale(const MatDesc& d, int kind, int t) {
   float amax;
@@ -1078,7 +1162,8 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
   typedef WaveCfg<P, BT> W;
   typedef typename AccT<C::ACC>::type Acc;
   constexpr int BK = P == kFP8 ? Fp8Cfg<BT>::KQ : (P == kBF16 ? DlCfg<BT>::BK : OpT<T>::kBK);
-  constexpr int LDSB = P == kFP8 ? Fp8Cfg<BT>::LDS : (P == kBF16 ? DlCfg<BT>::LDS : C::LDS);
+  constexpr bool DL = P == kBF16 || (P == kFP8 && BT == 256);  // direct-to-LDS operand ring
+  constexpr int LDSB = DL ? DlCfg<BT>::LDS : (P == kFP8 ? Fp8Cfg<BT>::LDS : C::LDS);
   __shared__ __attribute__((aligned(16))) char smem[LDSB];
   for (int slot = blockIdx.x; slot < args.total; slot += gridDim.x) {
     const int item = xcd_item(slot, args.total);
@@ -1096,7 +1181,8 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
       banded_decode(local, d.nb, d.nbL, &tm, &tn);
       const T* Bop = (const T*)d.Bs;
       const T* XTc = (const T*)((args.t & 1) ? d.XT1 : d.XT0);
-      if constexpr (P == kBF16)
+      // (the update always runs in bf16; the FP8 instantiation shares the bf16 loop)
+      if constexpr (DL)
         gemm_nt_tile_dl<BT>((const uint16_t*)Bop, (const uint16_t*)XTc, d.sp, tm * BT, tn * BT, 0, d.sp, smem, acc);
       else
         gemm_nt_tile<T, BT>(Bop, XTc, d.sp, tm * BT, tn * BT, 0, d.sp, smem, acc);
@@ -1121,7 +1207,11 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
       if constexpr (P == kFP8) {
         const float q = fp8_operand_scale(d, KIND, args.t);
         deq = 1.0f / (q * q);
-        if (k1 > k0) gemm_nt_tile_fp8<BT>(Op, Op, K, ti * BT, tj * BT, k0, k1, q, q, smem, acc);
+        if constexpr (BT == 256) {
+          if (k1 > k0) gemm_nt_tile_dl_fp8(Op, Op, K, ti * BT, tj * BT, k0, k1, q, q, smem, acc);
+        } else {
+          if (k1 > k0) gemm_nt_tile_fp8<BT>(Op, Op, K, ti * BT, tj * BT, k0, k1, q, q, smem, acc);
+        }
       } else if constexpr (P == kBF16) {
         if (k1 > k0)
           gemm_nt_tile_dl<BT>((const uint16_t*)Op, (const uint16_t*)Op, K, ti * BT, tj * BT, k0, k1, smem, acc);
