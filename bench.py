@@ -8,14 +8,17 @@ hipGraph).  Inputs are synthetic, seeded, resident in HBM before timing.
 Workloads:
   wide-batch        32-layer 4096-wide model: per layer four 4096x4096 and three
                     4096x14336 bf16 matrices (224), sigma_i = 1/i, Haar singular
-                    vectors, T = 5                                   (default)
+                    vectors, T = 5; the Gram-side products of steps 1-3 in e4m3
+                    with per-tensor scales, everything else bf16    (default)
   wide-layer        one layer of the above (7 matrices), for profiler runs
   gpt-small-batch   12 layers x {768x2304, 768x768, 768x3072, 3072x768} (48), sigma_i = 1/i
   single-4096x1024  one 4096x1024 bf16 matrix, log-uniform spectrum
 
 Metric: algorithmic TFLOP/s = sum over matrices and steps of (3 s^2 L + s^3)
 (s = min(m,n), L = max(m,n): Gram s^2 L, A^2 s^3 on the symmetric half, B X
-2 s^2 L) divided by the wall time of the step.
+2 s^2 L) divided by the wall time of the step.  pct_mfma_peak weights each
+product by the dense peak of its precision (bf16 2.5, e4m3 5.0 PFLOP/s).
+The comparison path runs the same matrices one plain bf16 call at a time.
 
 Prints ONE JSON line (rank 0, N = 1).
 """
@@ -109,10 +112,11 @@ def spec_norm_gpu(D, torch, iters=60):
 
 def measured_traffic(workload, compute, tile, fp8_steps):
     """HBM bytes per update launch from the committed counter runs, when they were
-    taken on this workload and on the kernel source as it is now (else None)."""
+    taken on this workload and on the kernel source as it is now (else None).  The
+    update runs in bf16 whether or not the Gram-side products of early steps use e4m3."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload.replace('-', '_')}.json")
-    if compute != "bf16" or tile != 0 or fp8_steps or not os.path.exists(path):
+    if compute == "f32" or tile != 0 or not os.path.exists(path):
         return None
     try:
         with open(path) as f:
@@ -152,8 +156,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="wide-batch",
                     choices=["wide-batch", "wide-layer", "gpt-small-batch", "single-4096x1024"])
-    ap.add_argument("--compute", default="bf16", choices=["bf16", "fp8", "f32"])
-    ap.add_argument("--fp8-steps", type=int, default=0)
+    ap.add_argument("--compute", default=None, choices=["bf16", "fp8", "f32"],
+                    help="default: fp8 (Gram-side steps 1-3) for wide-batch, bf16 otherwise")
+    ap.add_argument("--fp8-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-error", action="store_true")
@@ -165,6 +170,10 @@ def main():
                     help="first copy this many MiB device to device (a kernel of known traffic "
                          "that scales the HBM byte counters of a profiler run)")
     args = ap.parse_args()
+    if args.compute is None:
+        args.compute = "fp8" if args.workload == "wide-batch" else "bf16"
+    if args.fp8_steps is None:
+        args.fp8_steps = 3 if args.compute == "fp8" else 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(matrices would be sharded across GPUs with no exchange during the iteration)",
@@ -245,22 +254,26 @@ def main():
         log(f"[bench] ||X - UV^T||_2 on sampled matrices: {errs}")
 
     if not args.no_plain:
-        # plain single-matrix path: one eager pe_polar per matrix, same schedule
+        # plain single-matrix bf16 path: one eager pe_polar per matrix, same schedule
         outs = [torch.empty_like(G) for G in Gs]
         for G, X in zip(Gs[:2], outs[:2]):
-            pe.polar(G, T=T, abc=abc, compute=args.compute, out=X, fp8_steps=args.fp8_steps,
-                     tile=args.tile)
+            pe.polar(G, T=T, abc=abc, compute="bf16", out=X, tile=args.tile)
         torch.cuda.synchronize()
         e0.record(stream)
         for G, X in zip(Gs, outs):
-            pe.polar(G, T=T, abc=abc, compute=args.compute, out=X, fp8_steps=args.fp8_steps,
-                     tile=args.tile)
+            pe.polar(G, T=T, abc=abc, compute="bf16", out=X, tile=args.tile)
         e1.record(stream)
         torch.cuda.synchronize()
         plain_ms = e0.elapsed_time(e1)
-        extra["plain_single_matrix"] = dict(ms_per_step=round(plain_ms, 3),
+        extra["plain_single_matrix"] = dict(compute="bf16", ms_per_step=round(plain_ms, 3),
                                             tflops=round(flops / (plain_ms * 1e-3) / 1e12, 2))
-        log(f"[bench] plain path {plain_ms:.3f} ms/step")
+        if not args.no_error and "gaussian" not in meta:
+            perr = []
+            for idx in sorted(set([0, min(4, len(Gs) - 1)])):
+                P = polar_factor(meta, idx, torch).float()
+                perr.append(round(spec_norm_gpu(outs[idx].float() - P, torch), 5))
+            extra["plain_single_matrix"]["polar_err_sampled"] = perr
+        log(f"[bench] plain bf16 path {plain_ms:.3f} ms/step")
         del outs
 
     cpu = None
@@ -273,6 +286,14 @@ def main():
 
     peak = PEAK_BF16_TFLOPS
     traffic = measured_traffic(args.workload, args.compute, args.tile, args.fp8_steps)
+    # MFMA-peak fraction with each product at its own precision's dense peak
+    fp8_fl = 0.0
+    if args.compute == "fp8":
+        for m, n in shapes:
+            s_, L_ = min(m, n), max(m, n)
+            fp8_fl += (float(s_) * s_ * L_ + float(s_) ** 3) * min(args.fp8_steps, T)
+    pct_mfma = 100.0 * ((flops - fp8_fl) / (PEAK_BF16_TFLOPS * 1e12) +
+                        fp8_fl / (PEAK_FP8_TFLOPS * 1e12)) / (ms * 1e-3)
     out = {
         "metric": "polar TFLOP/s & % MFMA peak at fixed ||X-UV^T||_2, batched vs plain bf16",
         "value": round(tflops, 3),
@@ -290,6 +311,7 @@ def main():
                    "compute": args.compute, "fp8_steps": args.fp8_steps, "tile": args.tile,
                    "shapes": sorted(set(shapes))},
         "pct_bf16_peak": round(100.0 * tflops / peak, 2),
+        "pct_mfma_peak": round(pct_mfma, 2),
         "matrices_per_s": round(len(Gs) / (ms * 1e-3), 2),
         "roofline": {"bound": "mfma", "achieved": round(upd_tf, 2), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(upd_tf / peak, 4),

@@ -849,15 +849,15 @@ __device__ __forceinline__ void gemm_nt_tile_fp8(const uint16_t* __restrict__ P,
 }
 
 // ---------------------------------------- FP8 Gram-side main loop, 256 tile
-// The bf16 operand goes from HBM into the same LDS ring as on the bf16 path;
-// each lane converts the fragment it reads to e4m3 in registers and the block
-// runs v_mfma_scale_f32_32x32x64_f8f6f4 (FP32 accumulation).  One such MFMA
-// takes 64 k per row: lane l holds row l % 32 and k = 32 (l / 32) + 0..31,
-// i.e. one whole 32-k stage row, so stages are consumed in pairs (lanes 0-31
-// read the pair's first stage, lanes 32-63 its second).  The conversion
-// (v_cvt_scalef32_pk_fp8_bf16: e4m3(x / scale), round to nearest even, two
-// values per instruction) takes scale = 1/q, a power of two, so it yields
-// e4m3(q x) exactly as the quantiser does.
+// Once a step's operand maximum is known (X_t: the previous update or the norm
+// pass; A_t: the Gram epilogue), a quantisation pass writes its e4m3 copy
+// e4m3(q x) (quant_kernel); the product then streams one byte per element
+// through the direct-to-LDS ring (64 k per 64-byte row, one
+// v_mfma_scale_f32_32x32x64_f8f6f4 k-step per stage), half the bytes of the
+// bf16 ring, and the epilogue multiplies by 1/q^2.  The conversion
+// v_cvt_scalef32_pk_fp8_bf16 computes e4m3(x / scale) with round to nearest
+// even (two values per instruction); scale = 1/q, a power of two, makes it
+// e4m3(q x) exactly.
 __device__ __forceinline__ int cvt4_e4m3(uint32_t u0, uint32_t u1, float inv_q) {
   i16x2 r = {0, 0};
   r = __builtin_amdgcn_cvt_scalef32_pk_fp8_bf16(r, __builtin_bit_cast(bf16x2, u0), inv_q, false);
@@ -865,66 +865,97 @@ __device__ __forceinline__ int cvt4_e4m3(uint32_t u0, uint32_t u1, float inv_q) 
   return __builtin_bit_cast(int, r);
 }
 
-// one lane's 32 k of `row` of an operand stage (64-byte swizzled rows) as e4m3
-__device__ __forceinline__ i32x8 dl_row_e4m3(const char* op, int row, float inv_q) {
-  const char* r = op + row * 64;
-  i32x8 out;
+// Direct-to-LDS issue of one 64-k stage of two e4m3 operands (64 bytes per
+// row: the same row geometry and swizzle as a 32-k bf16 stage).
+__device__ __forceinline__ void dl_issue_stage_q8(const PE_GLOBAL uint8_t* P, const PE_GLOBAL uint8_t* Q,
+                                                  int64_t ld, int kofs, char* slot, int wave, int lane) {
+  typedef DlCfg<256> C;
 #pragma unroll
-  for (int ch = 0; ch < 4; ++ch) {
-    const u32x4 c = *(const u32x4*)(r + dl_swz(row, ch) * 16);
-    out[2 * ch] = cvt4_e4m3(c[0], c[1], inv_q);
-    out[2 * ch + 1] = cvt4_e4m3(c[2], c[3], inv_q);
+  for (int op = 0; op < 2; ++op) {
+    const PE_GLOBAL uint8_t* base = op == 0 ? P : Q;
+#pragma unroll
+    for (int j = 0; j < C::IPW; ++j) {
+      const int blk = wave * C::IPW + j;            // 1-KB block = 16 rows
+      const int row = blk * 16 + (lane >> 2);
+      const int lc = dl_swz(row, lane & 3);
+      const PE_GLOBAL uint8_t* g = base + (size_t)row * ld + kofs + lc * 16;
+      __builtin_amdgcn_global_load_lds((const void*)g,
+                                       (__attribute__((address_space(3))) void*)(slot + op * C::OPB + blk * 1024),
+                                       16, 0, 0);
+    }
   }
-  return out;
 }
 
-// acc += q(P)[rp0:+256, k0:k1] * q(Q)[rq0:+256, k0:k1]^T from bf16 operands in
-// HBM quantised to e4m3 with scales qp, qq; (k1 - k0) % 64 == 0.  The ring
-// holds two pairs: pair j+1 loads while pair j is converted and multiplied.
-// Each fragment is converted just before its MFMAs (an FP8 fragment is twice
-// the registers of a bf16 one, and 128 accumulators leave no room for a
-// second set); the other wave on the SIMD covers the LDS latency.
+// e4m3 fragments of one 64-k stage for v_mfma_scale_f32_32x32x64_f8f6f4:
+// lane l holds row l % 32 and k = 32 (l / 32) + 0..31, i.e. the 16-byte
+// chunks 2 (l / 32) and 2 (l / 32) + 1 of its 64-byte row.
+struct FragsQ8 {
+  i32x8 a[4], b[2];
+};
+
+__device__ __forceinline__ i32x8 q8_row(const char* op, int row, int kh) {
+  const char* r = op + row * 64;
+  const u32x4 c0 = *(const u32x4*)(r + dl_swz(row, 2 * kh) * 16);
+  const u32x4 c1 = *(const u32x4*)(r + dl_swz(row, 2 * kh + 1) * 16);
+  return i32x8{(int)c0[0], (int)c0[1], (int)c0[2], (int)c0[3], (int)c1[0], (int)c1[1], (int)c1[2], (int)c1[3]};
+}
+
+__device__ __forceinline__ void q8_read(const char* st, int wm, int wn, int lane, FragsQ8& f) {
+  constexpr int OPB = DlCfg<256>::OPB;
+  const int kh = lane >> 5;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) f.a[i] = q8_row(st, wm * 128 + i * 32 + (lane & 31), kh);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) f.b[i] = q8_row(st + OPB, wn * 64 + i * 32 + (lane & 31), kh);
+}
+
 template <typename A>
-__device__ __forceinline__ void gemm_nt_tile_dl_fp8(const uint16_t* __restrict__ P,
-                                                    const uint16_t* __restrict__ Q, int64_t ld,
-                                                    int rp0, int rq0, int k0, int k1, float qp,
-                                                    float qq, char* smem, A (&acc)[4][2]) {
+__device__ __forceinline__ void q8_mfma(const FragsQ8& f, A (&acc)[4][2]) {
+#pragma unroll
+  for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < 2; ++fn)
+      // format 0 = e4m3 for both operands, E8M0 block scales 127 = 1.0
+      acc[fm][fn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(f.a[fm], f.b[fn], acc[fm][fn],
+                                                                    0, 0, 0, 127, 0, 127);
+}
+
+// acc += P[rp0:+256, k0:k1] * Q[rq0:+256, k0:k1]^T with e4m3 operands in HBM
+// (already scaled by the quantisation pass); (k1 - k0) % 64 == 0.  Ring of
+// four 64-k stages (32 KB each), three in flight.  One fragment set per wave
+// (two would not fit beside the 128 accumulators); the second wave on each
+// SIMD covers the LDS latency.
+template <typename A>
+__device__ __forceinline__ void gemm_nt_tile_dl_q8(const uint8_t* __restrict__ P,
+                                                   const uint8_t* __restrict__ Q, int64_t ld, int rp0,
+                                                   int rq0, int k0, int k1, char* smem, A (&acc)[4][2]) {
   typedef DlCfg<256> C;
   typedef WaveCfg<kFP8, 256> W;
-  static_assert(W::NW == 8 && C::NS == 4 && C::LPS == 4, "pair ring of the 8-wave 256 tile");
-  constexpr int OPB = C::OPB;
+  static_assert(W::NW == 8 && C::NS == 4 && C::LPS == 4, "ring of the 8-wave 256 tile");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / W::WGN, wn = wave % W::WGN;
-  const PE_GLOBAL uint16_t* pP = gview(P) + (size_t)rp0 * ld + k0;
-  const PE_GLOBAL uint16_t* pQ = gview(Q) + (size_t)rq0 * ld + k0;
-  const float inv_qp = 1.0f / qp, inv_qq = 1.0f / qq;
-  const int nk = (k1 - k0) / C::BK;  // even
-  const int np = nk >> 1;
-  auto slot = [&](int s) { return smem + (s & 3) * C::STB; };
-  auto issue = [&](int s) {
-    const int ks = s < nk ? s : nk - 1;
-    dl_issue_stage<256>(pP, pQ, ld, ks * C::BK, slot(s), wave, lane);
-  };
+  const PE_GLOBAL uint8_t* pP = (const PE_GLOBAL uint8_t*)P + (size_t)rp0 * ld + k0;
+  const PE_GLOBAL uint8_t* pQ = (const PE_GLOBAL uint8_t*)Q + (size_t)rq0 * ld + k0;
+  const int nk = (k1 - k0) / 64;
   __syncthreads();  // the previous tile's readers are done with the ring
-  issue(0);
-  issue(1);
-  for (int j = 0; j < np; ++j) {
-    // own loads of pair j done; after the barrier everyone's are, and every
-    // wave has finished reading pair j-1, whose slots take pair j+1
-    wait_vmcnt<0>();
-    lds_barrier();
-    issue(2 * j + 2);
-    issue(2 * j + 3);
-    const char* st = (lane < 32) ? slot(2 * j) : slot(2 * j + 1);
-    i32x8 b0 = dl_row_e4m3(st + OPB, wn * 64 + (lane & 31), inv_qq);
-    i32x8 b1 = dl_row_e4m3(st + OPB, wn * 64 + 32 + (lane & 31), inv_qq);
 #pragma unroll
-    for (int fm = 0; fm < 4; ++fm) {
-      const i32x8 a = dl_row_e4m3(st, wm * 128 + fm * 32 + (lane & 31), inv_qp);
-      // format 0 = e4m3 for both operands, E8M0 block scales 127 = 1.0
-      acc[fm][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, acc[fm][0], 0, 0, 0, 127, 0, 127);
-      acc[fm][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, acc[fm][1], 0, 0, 0, 127, 0, 127);
+  for (int s = 0; s < 3; ++s) {
+    const int ks = s < nk ? s : nk - 1;
+    dl_issue_stage_q8(pP, pQ, ld, ks * 64, smem + s * C::STB, wave, lane);
+  }
+  for (int s = 0; s < nk; ++s) {
+    // own loads of stage s landed (stages s+1, s+2 may be pending); after the
+    // barrier everyone's have, and every wave has finished stage s-1, whose
+    // slot takes stage s+3
+    wait_vmcnt<2 * C::LPS>();
+    lds_barrier();
+    {
+      const int ks = s + 3 < nk ? s + 3 : nk - 1;
+      dl_issue_stage_q8(pP, pQ, ld, ks * 64, smem + ((s + 3) & 3) * C::STB, wave, lane);
     }
+    FragsQ8 f;
+    q8_read(smem + (s & 3) * C::STB, wm, wn, lane, f);
+    q8_mfma(f, acc);
   }
   wait_vmcnt<0>();  // no LDS write may still be in flight when the ring is reused
 }
@@ -1208,7 +1239,9 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
         const float q = fp8_operand_scale(d, KIND, args.t);
         deq = 1.0f / (q * q);
         if constexpr (BT == 256) {
-          if (k1 > k0) gemm_nt_tile_dl_fp8(Op, Op, K, ti * BT, tj * BT, k0, k1, q, q, smem, acc);
+          // e4m3 copies written by the quantisation pass (scale q already applied)
+          const uint8_t* Oq = KIND == KIND_GRAM ? d.Xq : d.Aq;
+          if (k1 > k0) gemm_nt_tile_dl_q8(Oq, Oq, K, ti * BT, tj * BT, k0, k1, smem, acc);
         } else {
           if (k1 > k0) gemm_nt_tile_fp8<BT>(Op, Op, K, ti * BT, tj * BT, k0, k1, q, q, smem, acc);
         }
@@ -1237,6 +1270,27 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
             }
       }
     }
+  }
+}
+
+// e4m3 copy of step t's Gram-side operand (KIND_GRAM: X_t from Xb into Xq;
+// KIND_A2: A_t from As into Aq) with the step's per-tensor scale.  One item is
+// 4096 elements (16 per thread); the padded sizes are multiples of 65536.
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void quant_kernel(KArgs args) {
+  for (int item = blockIdx.x; item < args.total; item += gridDim.x) {
+    const int mi = find_mat(args.offs, args.count, item);
+    const MatDesc& d = args.descs[mi];
+    if (skip_matrix(args, d)) continue;
+    const size_t e0 = ((size_t)(item - args.offs[mi]) * kThreads + threadIdx.x) * 16;
+    const uint16_t* src = (const uint16_t*)(KIND == KIND_GRAM ? d.Xb : d.As);
+    uint8_t* dst = KIND == KIND_GRAM ? d.Xq : d.Aq;
+    const float inv_q = 1.0f / fp8_operand_scale(d, KIND, args.t);
+    const u32x4 c0 = *(const PE_GLOBAL u32x4*)(gview(src) + e0);
+    const u32x4 c1 = *(const PE_GLOBAL u32x4*)(gview(src) + e0 + 8);
+    const u32x4 o = {(uint32_t)cvt4_e4m3(c0[0], c0[1], inv_q), (uint32_t)cvt4_e4m3(c0[2], c0[3], inv_q),
+                     (uint32_t)cvt4_e4m3(c1[0], c1[1], inv_q), (uint32_t)cvt4_e4m3(c1[2], c1[3], inv_q)};
+    *(u32x4*)(dst + e0) = o;
   }
 }
 
@@ -1349,6 +1403,13 @@ hipError_t launch_gemm(int prec, int bt, int kind, const KArgs& a, int grid_cap,
     if (bt == 256) launch_gemm_t<kBF16, 256>(kind, a, g, st);
     else launch_gemm_t<kBF16, 128>(kind, a, g, st);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_quant(int kind, const KArgs& a, int grid_cap, hipStream_t st) {
+  const int g = grid_for(a.total, grid_cap);
+  if (kind == KIND_GRAM) hipLaunchKernelGGL(quant_kernel<KIND_GRAM>, dim3(g), dim3(kThreads), 0, st, a);
+  else hipLaunchKernelGGL(quant_kernel<KIND_A2>, dim3(g), dim3(kThreads), 0, st, a);
   return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@
 //   As      sp x sp  bf16   A in bf16 on the bf16/fp8 paths, read by A^2 and by
 //                           the bA term of B (fp32 path: Af itself)
 //   Bs      sp x sp  bf16 or fp32   B = bA + cA^2
+//   Xq, Aq  sp x Lp, sp x sp  e4m3  operand copies for the FP8 steps (256 tile)
 //   part    split-K partial tiles of the Gram-side products
 //   red     per-tile partial sums of squares (fp64) and maxima (fp32) of G
 //   scal    per-matrix scalars (scale, amax values), cnt: arrival counters
@@ -68,6 +69,9 @@ struct MatDesc {
   float* feat;      // [16] features (diagnostic copy)
   float* est;       // [2]: estimate of ||X X^T - I||_2, flag
   float* vec;       // power iteration vectors: v [sp], y [sp], w [Lp]
+  // FP8 steps on the 256 tile: e4m3 copies of the Gram-side operands
+  uint8_t* Xq;      // sp x Lp: e4m3(q X_t), written by the quantisation pass
+  uint8_t* Aq;      // sp x sp: e4m3(q A_t)
 };
 
 struct KArgs {

@@ -25,6 +25,7 @@ hipError_t launch_put(const PutChunk& c, hipStream_t st);
 hipError_t launch_finalize(const KArgs& a, hipStream_t st);
 hipError_t launch_select(const KArgs& a, hipStream_t st);
 hipError_t launch_combine(int prec, const KArgs& a, hipStream_t st);
+hipError_t launch_quant(int kind, const KArgs& a, int grid_cap, hipStream_t st);
 hipError_t launch_est(const KArgs& a, int iters, hipStream_t st, const int32_t* offs_a, int total_a,
                       const int32_t* offs_b, int total_b);
 hipError_t launch_mlp_forward(const float* params, const float* feats, int B, float* logits,
@@ -45,7 +46,8 @@ namespace {
 
 thread_local std::string g_last_error;
 
-enum Phase { PH_PREP = 0, PH_GRAM, PH_A2, PH_UPD, PH_RGRAM, PH_RA2, PH_COMBINE, PH_EST_A, PH_EST_B, PH_N };
+enum Phase { PH_PREP = 0, PH_GRAM, PH_A2, PH_UPD, PH_RGRAM, PH_RA2, PH_COMBINE, PH_EST_A, PH_EST_B,
+             PH_QX, PH_QA, PH_N };
 
 constexpr double kClassEll[kClasses] = {1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5};
 constexpr int kFixedClass = 4;
@@ -57,6 +59,7 @@ constexpr int kGemmGridCap = 512;       // 128-tile kernel: 2 resident blocks pe
 constexpr int kGemmGridCapLarge = 256;  // 256-tile kernel: 1 resident block per CU
 constexpr int kPrepGridCap = 2048;
 constexpr int kReduceGridCap = 1024;
+constexpr int kQuantGridCap = 2048;
 constexpr int kFillTarget = 512;     // Gram-side items wanted per launch
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
@@ -199,6 +202,7 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
   L->offs_off = off;
   off = align_up(off + sizeof(int32_t) * (size_t)PH_N * (count + 1));
   const bool learned = learned_mode(o);
+  const bool q8 = prec == kBF16 && o->compute == PE_COMPUTE_FP8 && o->fp8_steps > 0 && bt == kTileLarge;
   L->coef_off = off;
   if (learned) off = align_up(off + sizeof(float) * kClasses * 3 * (size_t)o->T);
   for (int i = 0; i < count; ++i) {
@@ -258,6 +262,11 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
       d.red = (double*)take((size_t)q.prep * 12 + 16);
       d.scal = (float*)take(kScN * 4);
       d.cnt = (uint32_t*)take(64);  // reserved
+      // e4m3 operand copies of the FP8 steps (256 tile)
+      if (q8) {
+        d.Xq = (uint8_t*)take(X);
+        d.Aq = (uint8_t*)take(A);
+      }
       if (learned) {
         int32_t* ints = (int32_t*)take(64);
         d.selp = ints;
@@ -278,6 +287,9 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
     push(PH_RGRAM, (q.syrk && d.gram_split > 1) ? q.syrk : 0);
     push(PH_RA2, (q.syrk && d.a2_split > 1) ? q.syrk : 0);
     push(PH_COMBINE, (q.syrk && learned) ? (int)q.sp : 0);
+    // quantisation passes: 4096 elements per item
+    push(PH_QX, (q.syrk && q8) ? (int)((size_t)q.sp * q.Lp / 4096) : 0);
+    push(PH_QA, (q.syrk && q8) ? (int)((size_t)q.sp * q.sp / 4096) : 0);
     // power iteration: w = X^T v (length L), then y = X w (length s); a product
     // along the rows of the caller's m x n output takes one wave per row (4 per
     // block), one across its columns 64 columns per block
@@ -428,6 +440,13 @@ pe_status enqueue_gemm(const pe_plan* p, int t, int kind, hipStream_t st, int fa
   a.raw_a2 = p->learned && !fallback && t == 0 && kind == 1;
   // Gram-side products of the FP8 steps run the e4m3 kernels; updates stay bf16
   const int prec = (a.fp8 && kind != 2) ? kFP8 : p->prec;
+  if (prec == kFP8 && p->L.bt == kTileLarge) {
+    // the 256 tile reads e4m3 copies: quantise X_t (or A_t) with its scale first
+    set_phase(p, &a, kind == 0 ? PH_QX : PH_QA);
+    hipError_t e = launch_quant(kind, a, kQuantGridCap, st);
+    if (e != hipSuccess) return hip_fail(e, "quantisation launch");
+    set_phase(p, &a, ph_main[kind]);
+  }
   hipError_t e = launch_gemm(prec, p->L.bt, kind, a, p->L.bt == kTileLarge ? kGemmGridCapLarge : kGemmGridCap, st);
   if (e != hipSuccess) return hip_fail(e, names[kind]);
   if (ph_red[kind] >= 0 && p->L.totals[ph_red[kind]]) {
