@@ -1275,22 +1275,33 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
 
 // e4m3 copy of step t's Gram-side operand (KIND_GRAM: X_t from Xb into Xq;
 // KIND_A2: A_t from As into Aq) with the step's per-tensor scale.  One item is
-// 4096 elements (16 per thread); the padded sizes are multiples of 65536.
+// 16384 elements (four chunks of 16 per thread, all loads issued first); the
+// padded sizes are multiples of 65536.
 template <int KIND>
 __global__ __launch_bounds__(kThreads) void quant_kernel(KArgs args) {
+  constexpr int kChunks = 4;
   for (int item = blockIdx.x; item < args.total; item += gridDim.x) {
     const int mi = find_mat(args.offs, args.count, item);
     const MatDesc& d = args.descs[mi];
     if (skip_matrix(args, d)) continue;
-    const size_t e0 = ((size_t)(item - args.offs[mi]) * kThreads + threadIdx.x) * 16;
+    const size_t base = (size_t)(item - args.offs[mi]) * kChunks * kThreads * 16;
     const uint16_t* src = (const uint16_t*)(KIND == KIND_GRAM ? d.Xb : d.As);
     uint8_t* dst = KIND == KIND_GRAM ? d.Xq : d.Aq;
     const float inv_q = 1.0f / fp8_operand_scale(d, KIND, args.t);
-    const u32x4 c0 = *(const PE_GLOBAL u32x4*)(gview(src) + e0);
-    const u32x4 c1 = *(const PE_GLOBAL u32x4*)(gview(src) + e0 + 8);
-    const u32x4 o = {(uint32_t)cvt4_e4m3(c0[0], c0[1], inv_q), (uint32_t)cvt4_e4m3(c0[2], c0[3], inv_q),
-                     (uint32_t)cvt4_e4m3(c1[0], c1[1], inv_q), (uint32_t)cvt4_e4m3(c1[2], c1[3], inv_q)};
-    *(u32x4*)(dst + e0) = o;
+    u32x4 c[kChunks][2];
+#pragma unroll
+    for (int k = 0; k < kChunks; ++k) {
+      const size_t e0 = base + ((size_t)k * kThreads + threadIdx.x) * 16;
+      c[k][0] = *(const PE_GLOBAL u32x4*)(gview(src) + e0);
+      c[k][1] = *(const PE_GLOBAL u32x4*)(gview(src) + e0 + 8);
+    }
+#pragma unroll
+    for (int k = 0; k < kChunks; ++k) {
+      const size_t e0 = base + ((size_t)k * kThreads + threadIdx.x) * 16;
+      const u32x4 o = {(uint32_t)cvt4_e4m3(c[k][0][0], c[k][0][1], inv_q), (uint32_t)cvt4_e4m3(c[k][0][2], c[k][0][3], inv_q),
+                       (uint32_t)cvt4_e4m3(c[k][1][0], c[k][1][1], inv_q), (uint32_t)cvt4_e4m3(c[k][1][2], c[k][1][3], inv_q)};
+      *(u32x4*)(dst + e0) = o;
+    }
   }
 }
 

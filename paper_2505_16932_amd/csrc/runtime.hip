@@ -287,9 +287,9 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
     push(PH_RGRAM, (q.syrk && d.gram_split > 1) ? q.syrk : 0);
     push(PH_RA2, (q.syrk && d.a2_split > 1) ? q.syrk : 0);
     push(PH_COMBINE, (q.syrk && learned) ? (int)q.sp : 0);
-    // quantisation passes: 4096 elements per item
-    push(PH_QX, (q.syrk && q8) ? (int)((size_t)q.sp * q.Lp / 4096) : 0);
-    push(PH_QA, (q.syrk && q8) ? (int)((size_t)q.sp * q.sp / 4096) : 0);
+    // quantisation passes: 16384 elements per item (sizes are multiples of 65536)
+    push(PH_QX, (q.syrk && q8) ? (int)((size_t)q.sp * q.Lp / 16384) : 0);
+    push(PH_QA, (q.syrk && q8) ? (int)((size_t)q.sp * q.sp / 16384) : 0);
     // power iteration: w = X^T v (length L), then y = X w (length s); a product
     // along the rows of the caller's m x n output takes one wave per row (4 per
     // block), one across its columns 64 columns per block
