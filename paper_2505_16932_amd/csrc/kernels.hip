@@ -1349,11 +1349,20 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT)) void splitk_reduce_kernel(KAr
 }
 
 // q[i] = e4m3(x[i] * scale) with the conversion the FP8 path uses.
-__global__ void quantize_e4m3_kernel(const void* x, int x_bf16, uint8_t* q, int64_t n, float scale) {
+// bf16 input with a power-of-two scale takes the instruction of the FP8
+// steps' quantisation pass (e4m3(x / (1/scale)), exact); other inputs scale in
+// fp32 and convert with v_cvt_pk_fp8_f32.
+__global__ void quantize_e4m3_kernel(const void* x, int x_bf16, uint8_t* q, int64_t n, float scale,
+                                     int pow2) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const float v = x_bf16 ? bf2f(((const uint16_t*)x)[i]) : ((const float*)x)[i];
-    q[i] = (uint8_t)(pack4_e4m3(v * scale, 0.0f, 0.0f, 0.0f) & 0xffu);
+    if (x_bf16 && pow2) {
+      const uint32_t u = ((const uint16_t*)x)[i];
+      q[i] = (uint8_t)((uint32_t)cvt4_e4m3(u, 0u, 1.0f / scale) & 0xffu);
+    } else {
+      const float v = x_bf16 ? bf2f(((const uint16_t*)x)[i]) : ((const float*)x)[i];
+      q[i] = (uint8_t)(pack4_e4m3(v * scale, 0.0f, 0.0f, 0.0f) & 0xffu);
+    }
   }
 }
 
@@ -1443,7 +1452,9 @@ hipError_t launch_quantize(const void* x, int x_bf16, uint8_t* q, int64_t n, flo
                            hipStream_t st) {
   const int64_t blocks = (n + kThreads - 1) / kThreads;
   const int g = (int)(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096);
-  hipLaunchKernelGGL(quantize_e4m3_kernel, dim3(g), dim3(kThreads), 0, st, x, x_bf16, q, n, scale);
+  int e2 = 0;
+  const int pow2 = frexpf(scale, &e2) == 0.5f;
+  hipLaunchKernelGGL(quantize_e4m3_kernel, dim3(g), dim3(kThreads), 0, st, x, x_bf16, q, n, scale, pow2);
   return hipGetLastError();
 }
 

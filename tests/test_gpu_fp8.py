@@ -60,6 +60,22 @@ def test_quantizer_bf16_input(pe):
     assert np.array_equal(q.cpu().numpy(), LP.e4m3_code(vals * scale))
 
 
+@pytest.mark.parametrize("scale", [1.0, 2.0 ** 9, 2.0 ** -3])
+def test_quantizer_bf16_grid_scaled_conversion(pe, scale):
+    """bf16 input with a power-of-two scale runs the scaled bf16 -> e4m3
+    conversion of the FP8 steps' quantisation pass: every e4m3 magnitude, ties
+    and quarter points (after rounding the inputs to bf16), bit for bit."""
+    import torch
+    v = _grid_values() / scale
+    x = torch.from_numpy(v.astype(np.float32)).to(torch.bfloat16).cuda()
+    q = pe.quantize_e4m3(x, scale)
+    torch.cuda.synchronize()
+    vals = x.double().cpu().numpy()
+    got, ref = q.cpu().numpy(), LP.e4m3_code(vals * scale)
+    bad = np.flatnonzero(got != ref)
+    assert bad.size == 0, [(vals[i] * scale, got[i], ref[i]) for i in bad[:10]]
+
+
 FP8_CASES = [((768, 2304), 2, 3), ((768, 2304), 2, 1), ((3072, 768), 2, 3), ((3072, 768), 2, 2),
              ((384, 1000), 1, 3), ((384, 1000), 1, 1), ((130, 260), 1, 2), ((130, 260), 1, 1)]
 

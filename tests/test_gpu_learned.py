@@ -171,6 +171,32 @@ def test_learned_plan_large_tile_split_k(pe):
     plan.close()
 
 
+def test_learned_plan_with_fp8_steps(pe):
+    """The learned path combined with e4m3 Gram-side steps on the 256 tile: the
+    class is applied (forced), the result stays within the FP8 tolerance of the
+    FP64 iteration with that class's schedule, and graph replays reproduce it."""
+    import torch
+    from tests.gpu_util import oracle_same_iteration
+    G, v = _materialise(40, 768, 2304, synth.spectrum_powerlaw(768, 1.0))
+    abc4 = OS.greedy_schedule(1e-3, 5).abc
+    plan = pe.Plan([G], T=5, abc=abc4, compute="fp8", fp8_steps=3, force_class=2, tile=2,
+                   out_dtype=torch.float32)
+    plan.launch(graph=False)
+    torch.cuda.synchronize()
+    cls, _, _, _ = plan.selection()
+    assert cls.tolist() == [2]
+    ref = oracle_same_iteration(v, pe.coeffs(OM.CLASS_ELL[2], 5).abc)
+    err = relf(to_np(plan.outs[0]), ref)
+    print(f"[learned] fp8 steps 3, class 2: relF {err:.3e}", flush=True)
+    assert err <= 3e-2
+    eager = plan.outs[0].clone()
+    for _ in range(2):
+        plan.launch(graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(plan.outs[0], eager)
+    plan.close()
+
+
 @pytest.mark.parametrize("fill", [0x00, 0x3F, 0xFF])
 def test_learned_plan_ignores_workspace_contents(pe, fill):
     """The workspace needs no initialisation: whatever it held before (here
