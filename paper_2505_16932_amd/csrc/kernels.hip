@@ -1129,12 +1129,23 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
   }
 }
 
+// bf16 X^T tile of the 256 tile staged in the operand ring: 256 rows (n) of
+// 256 bf16 (i), padded to 528 bytes so a 16-byte-aligned row start spreads
+// the column-wise writes over the banks
+constexpr int kXtStageRow = 528;
+constexpr int kXtStageBytes = 256 * kXtStageRow;
+
 template <int P, int BT, bool LAST, typename A, int FN>
 __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, int tm, int tn,
-                                           const A (&acc)[4][FN]) {
+                                           const A (&acc)[4][FN], char* smem) {
   typedef TileCfg<BT> C;
   typedef WaveCfg<P, BT> W;
   static_assert(FN == W::FN, "accumulator grid");
+  // On the bf16 256 tile the transposed copy goes through LDS: written there
+  // column by column, then stored as whole 512-byte rows of X^T.  Stored
+  // directly, each 128-byte line of X^T would arrive in 16-byte pieces from
+  // different instructions and leave the L2 partly written.
+  constexpr bool kStageXt = !LAST && P != kF32 && BT == 256;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / W::WGN, wn = wave % W::WGN;
   float a, b, c;
@@ -1143,6 +1154,7 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
   const size_t Lp = d.Lp, sp = d.sp;
   void* XTn = (args.t & 1) ? d.XT0 : d.XT1;
   float amax = 0.0f;
+  if constexpr (kStageXt) __syncthreads();  // every wave is done with the operand ring
   FragRow<P, BT> pre[2];
   load_frag_row<P, BT>(d.Xf, Lp, tm * BT, tn * BT, wm, wn, 0, lane, pre[0]);
 #pragma unroll
@@ -1166,9 +1178,13 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
             if (P != kF32) ((uint16_t*)d.Xb)[o] = f2bf(v[r]);
             amax = fmaxf(amax, fabsf(v[r]));
           }
-          const size_t ot = (size_t)n * sp + i;
-          if (P == kF32) *(float4*)((float*)XTn + ot) = make_float4(v[0], v[1], v[2], v[3]);
-          else *(uint2*)((uint16_t*)XTn + ot) = pack4_bf16(v);
+          if constexpr (kStageXt) {
+            *(uint2*)(smem + (n - tn * BT) * kXtStageRow + (i - tm * BT) * 2) = pack4_bf16(v);
+          } else {
+            const size_t ot = (size_t)n * sp + i;
+            if (P == kF32) *(float4*)((float*)XTn + ot) = make_float4(v[0], v[1], v[2], v[3]);
+            else *(uint2*)((uint16_t*)XTn + ot) = pack4_bf16(v);
+          }
         } else if (n < d.L) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
@@ -1183,6 +1199,16 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
     }
   }
   if (!LAST && args.fp8_next) wave_amax_atomic(amax, d.scal + kScAmaxX + args.t + 1);
+  if constexpr (kStageXt) {
+    __syncthreads();
+    // 256 rows x 32 chunks of 16 bytes; consecutive threads take consecutive chunks of a row
+    uint16_t* xt = (uint16_t*)XTn + (size_t)tn * BT * sp + (size_t)tm * BT;
+    for (int ch = threadIdx.x; ch < 256 * 32; ch += W::NT) {
+      const int r = ch >> 5, cc = ch & 31;
+      *(u32x4*)(xt + (size_t)r * sp + cc * 8) = *(const u32x4*)(smem + r * kXtStageRow + cc * 16);
+    }
+    // (the next tile's prologue starts with a barrier before it refills the ring)
+  }
 }
 
 // ------------------------------------------------------------- kernels
@@ -1194,7 +1220,9 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
   typedef typename AccT<C::ACC>::type Acc;
   constexpr int BK = P == kFP8 ? Fp8Cfg<BT>::KQ : (P == kBF16 ? DlCfg<BT>::BK : OpT<T>::kBK);
   constexpr bool DL = P == kBF16 || (P == kFP8 && BT == 256);  // direct-to-LDS operand ring
-  constexpr int LDSB = DL ? DlCfg<BT>::LDS : (P == kFP8 ? Fp8Cfg<BT>::LDS : C::LDS);
+  constexpr int LDSB0 = DL ? DlCfg<BT>::LDS : (P == kFP8 ? Fp8Cfg<BT>::LDS : C::LDS);
+  // the update of the 256 tile stages its X^T tile in the same buffer
+  constexpr int LDSB = (KIND == KIND_UPD && BT == 256 && LDSB0 < kXtStageBytes) ? kXtStageBytes : LDSB0;
   __shared__ __attribute__((aligned(16))) char smem[LDSB];
   for (int slot = blockIdx.x; slot < args.total; slot += gridDim.x) {
     const int item = xcd_item(slot, args.total);
@@ -1217,7 +1245,7 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
         gemm_nt_tile_dl<BT>((const uint16_t*)Bop, (const uint16_t*)XTc, d.sp, tm * BT, tn * BT, 0, d.sp, smem, acc);
       else
         gemm_nt_tile<T, BT>(Bop, XTc, d.sp, tm * BT, tn * BT, 0, d.sp, smem, acc);
-      epi_update<P, BT, KIND == KIND_UPD_LAST>(args, d, tm, tn, acc);
+      epi_update<P, BT, KIND == KIND_UPD_LAST>(args, d, tm, tn, acc, smem);
     } else {
       const int split = KIND == KIND_GRAM ? d.gram_split : d.a2_split;
       const int tile = local / split, ksp = local % split;
