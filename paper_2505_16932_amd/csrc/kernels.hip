@@ -1226,10 +1226,10 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
   __shared__ __attribute__((aligned(16))) char smem[LDSB];
   for (int slot = blockIdx.x; slot < args.total; slot += gridDim.x) {
     const int item = xcd_item(slot, args.total);
-    const int mi = find_mat(args.offs, args.count, item);
-    const MatDesc& d = args.descs[mi];
+    const int pos = find_mat(args.offs, args.count, item);
+    const MatDesc& d = args.descs[args.ord ? args.ord[pos] : pos];
     if (skip_matrix(args, d)) continue;
-    const int local = item - args.offs[mi];
+    const int local = item - args.offs[pos];
     Acc acc[4][W::FN];
 #pragma unroll
     for (int fm = 0; fm < 4; ++fm)

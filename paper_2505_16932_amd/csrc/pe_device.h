@@ -94,6 +94,7 @@ struct KArgs {
   int32_t fixed_class;
   float tau;             // fallback threshold
   int32_t est_phase;     // power-iteration phase selector
+  const int32_t* ord;    // position -> matrix of this phase's item order (nullptr: identity)
 };
 
 constexpr int kClasses = 8;

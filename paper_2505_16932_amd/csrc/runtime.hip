@@ -78,6 +78,10 @@ struct Layout {
   int32_t totals[PH_N] = {0};
   size_t bytes = 0;
   size_t descs_off = 0, offs_off = 0, coef_off = 0;
+  // Gram items ordered by matrix, longest k (Lp) first: per-tile work is
+  // proportional to Lp, and persistent blocks take items round-robin, so
+  // long tiles first and short ones last balance the CUs
+  std::vector<int32_t> ord_gram;
   int bt = kTileSmall;
 };
 
@@ -200,7 +204,7 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
   L->descs_off = off;
   off = align_up(off + sizeof(MatDesc) * (size_t)std::max(count, 1));
   L->offs_off = off;
-  off = align_up(off + sizeof(int32_t) * (size_t)PH_N * (count + 1));
+  off = align_up(off + sizeof(int32_t) * ((size_t)PH_N * (count + 1) + count));
   const bool learned = learned_mode(o);
   const bool q8 = prec == kBF16 && o->compute == PE_COMPUTE_FP8 && o->fp8_steps > 0 && bt == kTileLarge;
   L->coef_off = off;
@@ -300,6 +304,19 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
       push(PH_EST_B, (q.syrk && learned) ? (t ? cols64 : rows4) : 0);
     }
   }
+  {
+    // Gram phase in longest-k-first matrix order (stable)
+    std::vector<int32_t> ord(count);
+    for (int i = 0; i < count; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return sh[x].Lp > sh[y].Lp; });
+    std::vector<int32_t> o(1, 0);
+    for (int k = 0; k < count; ++k) {
+      const int i = ord[k];
+      o.push_back(o.back() + (L->offs[PH_GRAM][i + 1] - L->offs[PH_GRAM][i]));
+    }
+    L->offs[PH_GRAM].swap(o);
+    L->ord_gram.swap(ord);
+  }
   for (int p = 0; p < PH_N; ++p) L->totals[p] = L->offs[p].back();
   L->bytes = off;
   return PE_OK;
@@ -367,6 +384,7 @@ pe_status upload(pe_plan* p, char* ws, hipStream_t st) {
   if (s != PE_OK) return s;
   std::vector<int32_t> offs;
   for (int ph = 0; ph < PH_N; ++ph) offs.insert(offs.end(), p->L.offs[ph].begin(), p->L.offs[ph].end());
+  offs.insert(offs.end(), p->L.ord_gram.begin(), p->L.ord_gram.end());
   s = put_words(p->d_offs, offs.data(), offs.size() * 4, st);
   if (s != PE_OK || !p->learned) return s;
   // schedule table of the classes: class 4 is the caller's schedule
@@ -404,6 +422,7 @@ KArgs base_args(const pe_plan* p) {
 
 void set_phase(const pe_plan* p, KArgs* a, int ph) {
   a->offs = p->d_offs + (size_t)ph * (p->count + 1);
+  a->ord = ph == PH_GRAM ? p->d_offs + (size_t)PH_N * (p->count + 1) : nullptr;
   a->total = p->L.totals[ph];
 }
 
