@@ -158,42 +158,50 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(KArgs args) {
   __shared__ float red_f[kThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rr = tid >> 3, cc = (tid & 7) * 8;
+  // one item = kPrepGroup consecutive 64 x 64 tiles (row-major tile order);
+  // the partial sums of an item are reduced once, in a fixed order
   for (int item = blockIdx.x; item < args.total; item += gridDim.x) {
     const int mi = find_mat(args.offs, args.count, item);
     const MatDesc& d = args.descs[mi];
     if (skip_matrix(args, d)) continue;
     const int local = item - args.offs[mi];
     const int ntk = d.Lp / kPrepTile;
-    const int i0 = (local / ntk) * kPrepTile;   // rows of X (s side)
-    const int k0 = (local % ntk) * kPrepTile;   // cols of X (L side)
-    // source block in G's own layout
-    const int sr0 = d.trans ? k0 : i0, sc0 = d.trans ? i0 : k0;
     const int srn = d.trans ? d.L : d.s, scn = d.trans ? d.s : d.L;
     double ss = 0.0;
     float amax = 0.0f;
+#pragma unroll 1
+    for (int u = 0; u < kPrepGroup; ++u) {
+      const int tix = local * kPrepGroup + u;
+      const int i0 = (tix / ntk) * kPrepTile;   // rows of X (s side)
+      const int k0 = (tix % ntk) * kPrepTile;   // cols of X (L side)
+      // source block in G's own layout
+      const int sr0 = d.trans ? k0 : i0, sc0 = d.trans ? i0 : k0;
+      float v[2][8];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int r = rr + 32 * j;
-      float v[8];
-      load8(d, sr0 + r, sc0 + cc, srn, scn, v);
+      for (int j = 0; j < 2; ++j) load8(d, sr0 + rr + 32 * j, sc0 + cc, srn, scn, v[j]);
+      if (u > 0) __syncthreads();  // the previous tile's transposed reads are done
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        tile[r][cc + e] = v[e];
-        ss += (double)v[e] * (double)v[e];
-        amax = fmaxf(amax, fabsf(v[e]));
+      for (int j = 0; j < 2; ++j) {
+        const int r = rr + 32 * j;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          tile[r][cc + e] = v[j][e];
+          ss += (double)v[j][e] * (double)v[j][e];
+          amax = fmaxf(amax, fabsf(v[j][e]));
+        }
+        if (!d.trans) store_x_chunk<P>(d, (size_t)(i0 + r) * d.Lp + k0 + cc, v[j]);
+        else store_xt_chunk<P>(d, (size_t)(k0 + r) * d.sp + i0 + cc, v[j]);
       }
-      if (!d.trans) store_x_chunk<P>(d, (size_t)(i0 + r) * d.Lp + k0 + cc, v);
-      else store_xt_chunk<P>(d, (size_t)(k0 + r) * d.sp + i0 + cc, v);
-    }
-    __syncthreads();
+      __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int q = rr + 32 * j;
-      float v[8];
+      for (int j = 0; j < 2; ++j) {
+        const int q = rr + 32 * j;
+        float w[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = tile[cc + e][q];
-      if (!d.trans) store_xt_chunk<P>(d, (size_t)(k0 + q) * d.sp + i0 + cc, v);
-      else store_x_chunk<P>(d, (size_t)(i0 + q) * d.Lp + k0 + cc, v);
+        for (int e = 0; e < 8; ++e) w[e] = tile[cc + e][q];
+        if (!d.trans) store_xt_chunk<P>(d, (size_t)(k0 + q) * d.sp + i0 + cc, w);
+        else store_x_chunk<P>(d, (size_t)(i0 + q) * d.Lp + k0 + cc, w);
+      }
     }
     for (int off = 32; off > 0; off >>= 1) {
       ss += __shfl_xor(ss, off);
@@ -205,6 +213,7 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(KArgs args) {
       d.red[local] = (red_d[0] + red_d[1]) + (red_d[2] + red_d[3]);
       ((float*)(d.red + d.n_prep))[local] = fmaxf(fmaxf(red_f[0], red_f[1]), fmaxf(red_f[2], red_f[3]));
     }
+    __syncthreads();  // the next item's first tile reuses the LDS tile and the reduction slots
   }
 }
 
@@ -1146,6 +1155,9 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
   // directly, each 128-byte line of X^T would arrive in 16-byte pieces from
   // different instructions and leave the L2 partly written.
   constexpr bool kStageXt = !LAST && P != kF32 && BT == 256;
+  // the last step stages a bf16 output tile the same way, in the caller's
+  // orientation, and stores whole rows (ragged edges element by element)
+  const bool stage_out = LAST && P != kF32 && BT == 256 && d.out_bf16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / W::WGN, wn = wave % W::WGN;
   float a, b, c;
@@ -1154,7 +1166,7 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
   const size_t Lp = d.Lp, sp = d.sp;
   void* XTn = (args.t & 1) ? d.XT0 : d.XT1;
   float amax = 0.0f;
-  if constexpr (kStageXt) __syncthreads();  // every wave is done with the operand ring
+  if (kStageXt || stage_out) __syncthreads();  // every wave is done with the operand ring
   FragRow<P, BT> pre[2];
   load_frag_row<P, BT>(d.Xf, Lp, tm * BT, tn * BT, wm, wn, 0, lane, pre[0]);
 #pragma unroll
@@ -1185,6 +1197,15 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
             if (P == kF32) *(float4*)((float*)XTn + ot) = make_float4(v[0], v[1], v[2], v[3]);
             else *(uint2*)((uint16_t*)XTn + ot) = pack4_bf16(v);
           }
+        } else if (stage_out) {
+          // tile-local (row, col) in the caller's layout: (i, n), or (n, i) when transposed
+          const int li = i - tm * BT, ln = n - tn * BT;
+          if (d.trans) {
+            *(uint2*)(smem + ln * kXtStageRow + li * 2) = pack4_bf16(v);
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) *(uint16_t*)(smem + (li + r) * kXtStageRow + ln * 2) = f2bf(v[r]);
+          }
         } else if (n < d.L) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
@@ -1209,6 +1230,25 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
     }
     // (the next tile's prologue starts with a barrier before it refills the ring)
   }
+  if (stage_out) {
+    __syncthreads();
+    // staged rows are output rows: i (or n when transposed) from the tile's first row
+    const int row0 = d.trans ? tn * BT : tm * BT, col0 = d.trans ? tm * BT : tn * BT;
+    const int rows = d.trans ? d.L : d.s, cols = d.trans ? d.s : d.L;
+    uint16_t* out = (uint16_t*)d.Out;
+    for (int ch = threadIdx.x; ch < 256 * 32; ch += W::NT) {
+      const int r = ch >> 5, c8 = (ch & 31) * 8;
+      const int gr = row0 + r, gc = col0 + c8;
+      if (gr >= rows || gc >= cols) continue;
+      const char* src = smem + r * kXtStageRow + c8 * 2;
+      uint16_t* dst = out + (size_t)gr * d.ldo + gc;
+      if (d.o_vec && gc + 8 <= cols) {
+        *(u32x4*)dst = *(const u32x4*)src;
+      } else {
+        for (int e = 0; e < 8 && gc + e < cols; ++e) dst[e] = ((const uint16_t*)src)[e];
+      }
+    }
+  }
 }
 
 // ------------------------------------------------------------- kernels
@@ -1222,7 +1262,8 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
   constexpr bool DL = P == kBF16 || (P == kFP8 && BT == 256);  // direct-to-LDS operand ring
   constexpr int LDSB0 = DL ? DlCfg<BT>::LDS : (P == kFP8 ? Fp8Cfg<BT>::LDS : C::LDS);
   // the update of the 256 tile stages its X^T tile in the same buffer
-  constexpr int LDSB = (KIND == KIND_UPD && BT == 256 && LDSB0 < kXtStageBytes) ? kXtStageBytes : LDSB0;
+  constexpr int LDSB = ((KIND == KIND_UPD || KIND == KIND_UPD_LAST) && BT == 256 && LDSB0 < kXtStageBytes)
+                           ? kXtStageBytes : LDSB0;
   __shared__ __attribute__((aligned(16))) char smem[LDSB];
   for (int slot = blockIdx.x; slot < args.total; slot += gridDim.x) {
     const int item = xcd_item(slot, args.total);

@@ -26,6 +26,7 @@ namespace pe {
 constexpr int kTileSmall = 128; // GEMM block tiles: 128 x 128 or 256 x 256
 constexpr int kTileLarge = 256;
 constexpr int kPrepTile = 64;   // norm/prep tile
+constexpr int kPrepGroup = 4;   // tiles per norm-pass item (one partial sum each)
 constexpr int kThreads = 256;   // threads per block (4 wave64)
 constexpr int kMaxSteps = 64;
 
@@ -60,7 +61,8 @@ struct MatDesc {
   float* scal;      // [kScN]
   uint32_t* cnt;    // [4]
   int32_t n_prep, syrk_nt, upd_nt, gram_split;
-  int32_t a2_split, bt, g_vec, pad2;  // bt: block tile edge; g_vec: 16-byte loads of G
+  int32_t a2_split, bt, g_vec, o_vec;  // bt: block tile edge; g_vec / o_vec: 16-byte
+                                       // loads of G / stores of the bf16 output
   // learned l-predictor (null unless the call selects schedules per matrix)
   int32_t* selp;    // schedule class of this matrix
   int32_t* flagp;   // 1: the fallback re-run recomputes this matrix

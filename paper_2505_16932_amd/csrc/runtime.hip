@@ -194,7 +194,8 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
       q.nbL = (int)(q.Lp / bt);
       q.syrk = q.nb * (q.nb + 1) / 2;
       q.upd = q.nb * q.nbL;
-      q.prep = (int)((q.sp / kPrepTile) * (q.Lp / kPrepTile));
+      // items of kPrepGroup tiles (sp and Lp are multiples of 128, so the tile count is a multiple of 4)
+      q.prep = (int)((q.sp / kPrepTile) * (q.Lp / kPrepTile) / kPrepGroup);
       syrk_total += q.syrk;
     }
     sh.push_back(q);
@@ -233,6 +234,7 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
       d.g_vec = ((uintptr_t)m.G % 16 == 0) && (m.ldg % per16 == 0);
     }
     d.out_bf16 = m.x_dtype == PE_BF16;
+    d.o_vec = d.out_bf16 && ((uintptr_t)m.X % 16 == 0) && (m.ldx % 8 == 0);
     d.nb = q.nb;
     d.nbL = q.nbL;
     d.bt = bt;

@@ -239,3 +239,26 @@ def test_tiles_agree(pe, torch_cuda):
     X2 = pe.polar(G, T=5, compute="bf16", out_dtype=torch_cuda.float32, tile=2)
     torch_cuda.cuda.synchronize()
     assert relf(to_np(X2), to_np(X1)) <= 2e-2
+
+
+@pytest.mark.parametrize("shape", [(600, 1100), (1100, 600), (512, 768), (777, 513)])
+def test_large_tile_bf16_output_equals_rounded_fp32(pe, torch_cuda, shape):
+    """The 256 tile stages a bf16 output tile in LDS and stores whole rows
+    (16-byte stores when aligned, element by element at ragged edges): for the
+    same call it must equal the FP32 output rounded to bf16, bit for bit, wide
+    and tall, and with an output whose leading dimension rules out 16-byte
+    stores."""
+    import torch
+    G64 = synth.powerlaw(1200 + shape[0], *shape).G
+    G, _ = device_input(G64, torch.bfloat16)
+    abc = oracle_schedule(5)
+    X32 = pe.polar(G, T=5, abc=abc, compute="bf16", out_dtype=torch.float32, tile=2)
+    X16 = pe.polar(G, T=5, abc=abc, compute="bf16", out_dtype=torch.bfloat16, tile=2)
+    big = torch.zeros((shape[0], shape[1] + 3), dtype=torch.bfloat16, device="cuda")
+    Xs = big[:, :shape[1]]
+    pe.polar(G, T=5, abc=abc, compute="bf16", out=Xs, tile=2)
+    torch.cuda.synchronize()
+    ref = X32.to(torch.bfloat16)
+    assert torch.equal(X16, ref)
+    assert torch.equal(Xs, ref)
+    assert torch.count_nonzero(big[:, shape[1]:]) == 0   # nothing written past the columns
