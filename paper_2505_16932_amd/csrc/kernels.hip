@@ -37,6 +37,16 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef short i16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Streaming (non-temporal) stores and loads, for data that a launch touches
+// once: outputs that only later launches read should not displace from the L2
+// the operand panels that neighbouring tiles of the same launch re-read.
+template <typename T>
+__device__ __forceinline__ void st_stream(T* p, T v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_stream(uint2* p, uint2 v) {
+  __builtin_nontemporal_store((u32x2){v.x, v.y}, (u32x2*)p);
+}
 
 enum Kind : int { KIND_GRAM = 0, KIND_A2 = 1, KIND_UPD = 2, KIND_UPD_LAST = 3 };
 
@@ -128,14 +138,14 @@ __device__ __forceinline__ void load8(const MatDesc& d, int gr, int gc, int srn,
 
 template <int P>
 __device__ __forceinline__ void store8_f32(float* dst, const float (&v)[8]) {
-  *(f32x4*)dst = f32x4{v[0], v[1], v[2], v[3]};
-  *(f32x4*)(dst + 4) = f32x4{v[4], v[5], v[6], v[7]};
+  st_stream((f32x4*)dst, f32x4{v[0], v[1], v[2], v[3]});
+  st_stream((f32x4*)(dst + 4), f32x4{v[4], v[5], v[6], v[7]});
 }
 __device__ __forceinline__ void store8_bf16(uint16_t* dst, const float (&v)[8]) {
   u32x4 w;
 #pragma unroll
   for (int e = 0; e < 4; ++e) w[e] = (uint32_t)f2bf(v[2 * e]) | ((uint32_t)f2bf(v[2 * e + 1]) << 16);
-  *(u32x4*)dst = w;
+  st_stream((u32x4*)dst, w);
 }
 
 // row-major X row chunk: fp32 master and (bf16 paths) the bf16 operand copy
@@ -1007,14 +1017,15 @@ struct FragRow {
   float x[WaveCfg<P, BT>::FN][TileCfg<BT>::RG][4];  // [fn][row group][r]
 };
 
-template <typename S>
+template <bool NT, typename S>
 __device__ __forceinline__ float load_as_float(const S* p) {
-  if constexpr (sizeof(S) == 2) return bf2f(*p);
-  else return *p;
+  const S v = NT ? __builtin_nontemporal_load(p) : *p;
+  if constexpr (sizeof(S) == 2) return bf2f(v);
+  else return v;
 }
 
-// S = float or uint16_t (bf16)
-template <int P, int BT, typename S>
+// S = float or uint16_t (bf16); NT: streaming loads (data read once per launch)
+template <int P, int BT, typename S, bool NT = false>
 __device__ __forceinline__ void load_frag_row(const S* __restrict__ src, size_t ld, int row0,
                                               int col0, int wm, int wn, int fm, int lane,
                                               FragRow<P, BT>& f) {
@@ -1024,7 +1035,7 @@ __device__ __forceinline__ void load_frag_row(const S* __restrict__ src, size_t 
     for (int g = 0; g < TileCfg<BT>::RG; ++g) {
       const size_t o = (size_t)(row0 + acc_row<BT>(wm, fm, g, lane)) * ld + col0 + acc_col<P, BT>(wn, fn, lane);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) f.x[fn][g][r] = load_as_float(src + o + (size_t)r * ld);
+      for (int r = 0; r < 4; ++r) f.x[fn][g][r] = load_as_float<NT>(src + o + (size_t)r * ld);
     }
 }
 
@@ -1032,9 +1043,20 @@ __device__ __forceinline__ void load_frag_row(const S* __restrict__ src, size_t 
 // GEMM kernel lends its operand ring, free once the main loop is done; a
 // kernel with a single LDS object keeps the compiler's LDS-DMA wait tracking
 // from turning into a full vmcnt(0) wait after every stage's loads).
-template <int P, int BT, typename A, int FN>
+// A transposed bf16 tile of the 256 tile (the update's X^T, a SYRK tile's
+// mirror) staged in the operand ring: 256 rows of 256 bf16, padded to 528
+// bytes so a 16-byte-aligned row start spreads the column-wise writes over the
+// banks
+constexpr int kXtStageRow = 528;
+constexpr int kXtStageBytes = 256 * kXtStageRow;
+
+// STAGE (bf16 operands of the 256 tile): an off-diagonal tile's mirror is
+// written to LDS column by column and stored as whole rows; stored directly,
+// it would leave the L2 in 8-byte pieces from 64 different rows per instruction.
+template <int P, int BT, bool STAGE, typename A, int FN>
 __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, int kind, int ti,
-                                         int tj, float deq, const A (&acc)[4][FN], double* red) {
+                                         int tj, float deq, const A (&acc)[4][FN], double* red,
+                                         char* smem) {
   typedef TileCfg<BT> C;
   typedef WaveCfg<P, BT> W;
   static_assert(FN == W::FN, "accumulator grid");
@@ -1056,6 +1078,9 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
   const bool reads_a = kind == KIND_A2;
   typedef typename std::conditional<P == kF32, float, uint16_t>::type AT;
   const AT* Asrc = P == kF32 ? (const AT*)d.Af : (const AT*)d.As;
+  static_assert(!STAGE || (P != kF32 && BT == 256), "mirror staging: bf16 tiles of 256");
+  const bool stage = STAGE && ti != tj && !(kind == KIND_A2 && args.raw_a2);
+  if (stage) __syncthreads();  // every wave is done with the operand ring
   FragRow<P, BT> pre[2];
   if (reads_a) load_frag_row<P, BT>(Asrc, sp, ti * BT, tj * BT, wm, wn, 0, lane, pre[0]);
 #pragma unroll
@@ -1099,6 +1124,8 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
         }
         if (ti != tj && kind == KIND_A2 && args.raw_a2) {
           *(float4*)(d.A2f + (size_t)j * sp + i) = make_float4(v[0], v[1], v[2], v[3]);
+        } else if (stage) {
+          *(uint2*)(smem + (j - tj * BT) * kXtStageRow + (i - ti * BT) * 2) = pack4_bf16(v);
         } else if (ti != tj) {
           // mirrored tile: row j, columns i..i+3 (contiguous)
           const size_t o = (size_t)j * sp + i;
@@ -1112,6 +1139,16 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
         }
       }
     }
+  }
+  if (stage) {
+    __syncthreads();
+    // mirror rows j = tj*BT + r, columns ti*BT .. +255: 256 rows x 32 chunks of 16 bytes
+    uint16_t* mir = (uint16_t*)(kind == KIND_GRAM ? d.As : d.Bs) + (size_t)tj * BT * sp + (size_t)ti * BT;
+    for (int ch = threadIdx.x; ch < 256 * 32; ch += W::NT) {
+      const int r = ch >> 5, cc = ch & 31;
+      *(u32x4*)(mir + (size_t)r * sp + cc * 8) = *(const u32x4*)(smem + r * kXtStageRow + cc * 16);
+    }
+    // (the next tile's prologue starts with a barrier before it refills the ring)
   }
   // the A^2 product of the same step quantises A with this maximum
   if (kind == KIND_GRAM && args.fp8) wave_amax_atomic(amax, d.scal + kScAmaxA + args.t);
@@ -1138,11 +1175,6 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
   }
 }
 
-// bf16 X^T tile of the 256 tile staged in the operand ring: 256 rows (n) of
-// 256 bf16 (i), padded to 528 bytes so a 16-byte-aligned row start spreads
-// the column-wise writes over the banks
-constexpr int kXtStageRow = 528;
-constexpr int kXtStageBytes = 256 * kXtStageRow;
 
 template <int P, int BT, bool LAST, typename A, int FN>
 __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, int tm, int tn,
@@ -1168,10 +1200,11 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
   float amax = 0.0f;
   if (kStageXt || stage_out) __syncthreads();  // every wave is done with the operand ring
   FragRow<P, BT> pre[2];
-  load_frag_row<P, BT>(d.Xf, Lp, tm * BT, tn * BT, wm, wn, 0, lane, pre[0]);
+  load_frag_row<P, BT, float, true>(d.Xf, Lp, tm * BT, tn * BT, wm, wn, 0, lane, pre[0]);
 #pragma unroll
   for (int fm = 0; fm < 4; ++fm) {
-    if (fm + 1 < 4) load_frag_row<P, BT>(d.Xf, Lp, tm * BT, tn * BT, wm, wn, fm + 1, lane, pre[(fm + 1) & 1]);
+    if (fm + 1 < 4)
+      load_frag_row<P, BT, float, true>(d.Xf, Lp, tm * BT, tn * BT, wm, wn, fm + 1, lane, pre[(fm + 1) & 1]);
     const FragRow<P, BT>& cur = pre[fm & 1];
 #pragma unroll
     for (int fn = 0; fn < FN; ++fn) {
@@ -1186,7 +1219,7 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const size_t o = (size_t)(i + r) * Lp + n;
-            d.Xf[o] = v[r];
+            st_stream(d.Xf + o, v[r]);
             if (P != kF32) ((uint16_t*)d.Xb)[o] = f2bf(v[r]);
             amax = fmaxf(amax, fabsf(v[r]));
           }
@@ -1194,8 +1227,8 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
             *(uint2*)(smem + (n - tn * BT) * kXtStageRow + (i - tm * BT) * 2) = pack4_bf16(v);
           } else {
             const size_t ot = (size_t)n * sp + i;
-            if (P == kF32) *(float4*)((float*)XTn + ot) = make_float4(v[0], v[1], v[2], v[3]);
-            else *(uint2*)((uint16_t*)XTn + ot) = pack4_bf16(v);
+            if (P == kF32) st_stream((f32x4*)((float*)XTn + ot), (f32x4){v[0], v[1], v[2], v[3]});
+            else st_stream((uint2*)((uint16_t*)XTn + ot), pack4_bf16(v));
           }
         } else if (stage_out) {
           // tile-local (row, col) in the caller's layout: (i, n), or (n, i) when transposed
@@ -1211,8 +1244,8 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
           for (int r = 0; r < 4; ++r) {
             if (i + r < d.s) {
               const size_t o = d.trans ? (size_t)n * d.ldo + (i + r) : (size_t)(i + r) * d.ldo + n;
-              if (d.out_bf16) ((uint16_t*)d.Out)[o] = f2bf(v[r]);
-              else ((float*)d.Out)[o] = v[r];
+              if (d.out_bf16) st_stream((uint16_t*)d.Out + o, f2bf(v[r]));
+              else st_stream((float*)d.Out + o, v[r]);
             }
           }
         }
@@ -1226,7 +1259,7 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
     uint16_t* xt = (uint16_t*)XTn + (size_t)tn * BT * sp + (size_t)tm * BT;
     for (int ch = threadIdx.x; ch < 256 * 32; ch += W::NT) {
       const int r = ch >> 5, cc = ch & 31;
-      *(u32x4*)(xt + (size_t)r * sp + cc * 8) = *(const u32x4*)(smem + r * kXtStageRow + cc * 16);
+      st_stream((u32x4*)(xt + (size_t)r * sp + cc * 8), *(const u32x4*)(smem + r * kXtStageRow + cc * 16));
     }
     // (the next tile's prologue starts with a barrier before it refills the ring)
   }
@@ -1243,9 +1276,9 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
       const char* src = smem + r * kXtStageRow + c8 * 2;
       uint16_t* dst = out + (size_t)gr * d.ldo + gc;
       if (d.o_vec && gc + 8 <= cols) {
-        *(u32x4*)dst = *(const u32x4*)src;
+        st_stream((u32x4*)dst, *(const u32x4*)src);
       } else {
-        for (int e = 0; e < 8 && gc + e < cols; ++e) dst[e] = ((const uint16_t*)src)[e];
+        for (int e = 0; e < 8 && gc + e < cols; ++e) st_stream(dst + e, ((const uint16_t*)src)[e]);
       }
     }
   }
@@ -1261,9 +1294,11 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
   constexpr int BK = P == kFP8 ? Fp8Cfg<BT>::KQ : (P == kBF16 ? DlCfg<BT>::BK : OpT<T>::kBK);
   constexpr bool DL = P == kBF16 || (P == kFP8 && BT == 256);  // direct-to-LDS operand ring
   constexpr int LDSB0 = DL ? DlCfg<BT>::LDS : (P == kFP8 ? Fp8Cfg<BT>::LDS : C::LDS);
-  // the update of the 256 tile stages its X^T tile in the same buffer
-  constexpr int LDSB = ((KIND == KIND_UPD || KIND == KIND_UPD_LAST) && BT == 256 && LDSB0 < kXtStageBytes)
-                           ? kXtStageBytes : LDSB0;
+  // the 256 tile stages transposed bf16 tiles (the update's X^T, a SYRK
+  // tile's mirror) in the same buffer
+  constexpr bool kStageMirror = P != kF32 && BT == 256;
+  constexpr int LDSB = (BT == 256 && (P != kF32 || KIND == KIND_UPD || KIND == KIND_UPD_LAST) &&
+                        LDSB0 < kXtStageBytes) ? kXtStageBytes : LDSB0;
   __shared__ __attribute__((aligned(16))) char smem[LDSB];
   for (int slot = blockIdx.x; slot < args.total; slot += gridDim.x) {
     const int item = xcd_item(slot, args.total);
@@ -1321,7 +1356,7 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
         if (k1 > k0) gemm_nt_tile<T, BT>(Op, Op, K, ti * BT, tj * BT, k0, k1, smem, acc);
       }
       if (split == 1) {
-        epi_syrk<P, BT>(args, d, KIND, ti, tj, deq, acc, (double*)smem);
+        epi_syrk<P, BT, kStageMirror>(args, d, KIND, ti, tj, deq, acc, (double*)smem, smem);
       } else {
         // partial tile: float4 q of thread t at ((tile*split + ksp)*Q + q)*NT + t
         constexpr int Q = 4 * W::FN * C::ACC / 4;
@@ -1369,7 +1404,7 @@ __global__ __launch_bounds__(kThreads) void quant_kernel(KArgs args) {
       const size_t e0 = base + ((size_t)k * kThreads + threadIdx.x) * 16;
       const u32x4 o = {(uint32_t)cvt4_e4m3(c[k][0][0], c[k][0][1], inv_q), (uint32_t)cvt4_e4m3(c[k][0][2], c[k][0][3], inv_q),
                        (uint32_t)cvt4_e4m3(c[k][1][0], c[k][1][1], inv_q), (uint32_t)cvt4_e4m3(c[k][1][2], c[k][1][3], inv_q)};
-      *(u32x4*)(dst + e0) = o;
+      st_stream((u32x4*)(dst + e0), o);
     }
   }
 }
@@ -1413,7 +1448,7 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT)) void splitk_reduce_kernel(KAr
       const float q = fp8_operand_scale(d, KIND, args.t);
       deq = 1.0f / (q * q);
     }
-    epi_syrk<P, BT>(args, d, KIND, ti, tj, deq, acc, red);
+    epi_syrk<P, BT, false>(args, d, KIND, ti, tj, deq, acc, red, nullptr);
   }
 }
 
