@@ -1043,6 +1043,27 @@ __device__ __forceinline__ void load_frag_row(const S* __restrict__ src, size_t 
 // GEMM kernel lends its operand ring, free once the main loop is done; a
 // kernel with a single LDS object keeps the compiler's LDS-DMA wait tracking
 // from turning into a full vmcnt(0) wait after every stage's loads).
+// A is exactly symmetric as stored (a tile's mirror holds the same bf16
+// values, and a diagonal tile sums the same products in the same order at (i,j)
+// and (j,i)), so the four consecutive rows i..i+3 of a lane at column j are the
+// contiguous A[j][i..i+3]: one 8-byte load instead of four 2-byte ones.
+template <int P, int BT>
+__device__ __forceinline__ void load_frag_row_sym(const uint16_t* __restrict__ A, size_t ld, int row0,
+                                                  int col0, int wm, int wn, int fm, int lane,
+                                                  FragRow<P, BT>& f) {
+#pragma unroll
+  for (int fn = 0; fn < WaveCfg<P, BT>::FN; ++fn)
+#pragma unroll
+    for (int g = 0; g < TileCfg<BT>::RG; ++g) {
+      const size_t o = (size_t)(col0 + acc_col<P, BT>(wn, fn, lane)) * ld + row0 + acc_row<BT>(wm, fm, g, lane);
+      const u32x2 w = *gview((const u32x2*)(A + o));
+      f.x[fn][g][0] = __uint_as_float(w[0] << 16);
+      f.x[fn][g][1] = __uint_as_float(w[0] & 0xffff0000u);
+      f.x[fn][g][2] = __uint_as_float(w[1] << 16);
+      f.x[fn][g][3] = __uint_as_float(w[1] & 0xffff0000u);
+    }
+}
+
 // A transposed bf16 tile of the 256 tile (the update's X^T, a SYRK tile's
 // mirror) staged in the operand ring: 256 rows of 256 bf16, padded to 528
 // bytes so a 16-byte-aligned row start spreads the column-wise writes over the
@@ -1082,10 +1103,14 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
   const bool stage = STAGE && ti != tj && !(kind == KIND_A2 && args.raw_a2);
   if (stage) __syncthreads();  // every wave is done with the operand ring
   FragRow<P, BT> pre[2];
-  if (reads_a) load_frag_row<P, BT>(Asrc, sp, ti * BT, tj * BT, wm, wn, 0, lane, pre[0]);
+  auto load_a = [&](int fm, FragRow<P, BT>& f) {
+    if constexpr (P == kF32) load_frag_row<P, BT>(Asrc, sp, ti * BT, tj * BT, wm, wn, fm, lane, f);
+    else load_frag_row_sym<P, BT>((const uint16_t*)Asrc, sp, ti * BT, tj * BT, wm, wn, fm, lane, f);
+  };
+  if (reads_a) load_a(0, pre[0]);
 #pragma unroll
   for (int fm = 0; fm < 4; ++fm) {
-    if (reads_a && fm + 1 < 4) load_frag_row<P, BT>(Asrc, sp, ti * BT, tj * BT, wm, wn, fm + 1, lane, pre[(fm + 1) & 1]);
+    if (reads_a && fm + 1 < 4) load_a(fm + 1, pre[(fm + 1) & 1]);
     const FragRow<P, BT>& cur = pre[fm & 1];
 #pragma unroll
     for (int fn = 0; fn < FN; ++fn) {

@@ -171,6 +171,30 @@ def test_learned_plan_large_tile_split_k(pe):
     plan.close()
 
 
+@pytest.mark.parametrize("tile,m,n", [(1, 384, 640), (2, 512, 768)])
+def test_combine_equals_a2_epilogue_bit_for_bit(pe, tile, m, n):
+    """B = bA + cA^2 formed two ways gives the same bits: the learned path's
+    combine kernel reads A row by row, the A^2 epilogue of the plain path reads
+    A at the mirrored position (four rows of a column as one contiguous load).
+    Equal outputs show that the stored A, diagonal tiles included, is exactly
+    symmetric, which the mirrored read relies on."""
+    import torch
+    G, _ = _materialise(50 + tile, m, n, synth.spectrum_powerlaw(m, 1.0))
+    abc4 = OS.greedy_schedule(1e-3, 5).abc
+    plan = pe.Plan([G], T=5, abc=abc4, compute="bf16", force_class=2, tile=tile, out_dtype=torch.float32)
+    plan.launch(graph=False)
+    torch.cuda.synchronize()
+    cls, _, _, flags = plan.selection()
+    assert cls.tolist() == [2] and flags.tolist() == [0]
+    Y = pe.polar(G, T=5, abc=pe.coeffs(OM.CLASS_ELL[2], 5).abc, compute="bf16", tile=tile,
+                 out_dtype=torch.float32)
+    torch.cuda.synchronize()
+    diff = (plan.outs[0] - Y).abs().max().item()
+    print(f"[learned] tile {tile} {m}x{n}: max |combine path - epilogue path| = {diff:.3e}", flush=True)
+    assert torch.equal(plan.outs[0], Y)
+    plan.close()
+
+
 def test_learned_plan_with_fp8_steps(pe):
     """The learned path combined with e4m3 Gram-side steps on the 256 tile: the
     class is applied (forced), the result stays within the FP8 tolerance of the
