@@ -47,6 +47,12 @@ __device__ __forceinline__ void st_stream(T* p, T v) { __builtin_nontemporal_sto
 __device__ __forceinline__ void st_stream(uint2* p, uint2 v) {
   __builtin_nontemporal_store((u32x2){v.x, v.y}, (u32x2*)p);
 }
+// streaming only where S holds; an ordinary store otherwise
+template <bool S, typename T>
+__device__ __forceinline__ void st_hint(T* p, T v) {
+  if constexpr (S) st_stream(p, v);
+  else *p = v;
+}
 
 enum Kind : int { KIND_GRAM = 0, KIND_A2 = 1, KIND_UPD = 2, KIND_UPD_LAST = 3 };
 
@@ -1215,6 +1221,12 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
   // the last step stages a bf16 output tile the same way, in the caller's
   // orientation, and stores whole rows (ragged edges element by element)
   const bool stage_out = LAST && P != kF32 && BT == 256 && d.out_bf16;
+  // Streaming loads and stores on the 256 tile, which serves matrices whose
+  // iterates are far larger than the caches: its outputs are read by later
+  // launches only, and streaming keeps the L2 for the operand panels.  The 128
+  // tile serves small matrices, whose working set stays in the caches from one
+  // launch to the next, so it keeps ordinary loads and stores.
+  constexpr bool kStream = BT == 256;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / W::WGN, wn = wave % W::WGN;
   float a, b, c;
@@ -1225,11 +1237,11 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
   float amax = 0.0f;
   if (kStageXt || stage_out) __syncthreads();  // every wave is done with the operand ring
   FragRow<P, BT> pre[2];
-  load_frag_row<P, BT, float, true>(d.Xf, Lp, tm * BT, tn * BT, wm, wn, 0, lane, pre[0]);
+  load_frag_row<P, BT, float, kStream>(d.Xf, Lp, tm * BT, tn * BT, wm, wn, 0, lane, pre[0]);
 #pragma unroll
   for (int fm = 0; fm < 4; ++fm) {
     if (fm + 1 < 4)
-      load_frag_row<P, BT, float, true>(d.Xf, Lp, tm * BT, tn * BT, wm, wn, fm + 1, lane, pre[(fm + 1) & 1]);
+      load_frag_row<P, BT, float, kStream>(d.Xf, Lp, tm * BT, tn * BT, wm, wn, fm + 1, lane, pre[(fm + 1) & 1]);
     const FragRow<P, BT>& cur = pre[fm & 1];
 #pragma unroll
     for (int fn = 0; fn < FN; ++fn) {
@@ -1244,7 +1256,7 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const size_t o = (size_t)(i + r) * Lp + n;
-            st_stream(d.Xf + o, v[r]);
+            st_hint<kStream>(d.Xf + o, v[r]);
             if (P != kF32) ((uint16_t*)d.Xb)[o] = f2bf(v[r]);
             amax = fmaxf(amax, fabsf(v[r]));
           }
@@ -1252,8 +1264,8 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
             *(uint2*)(smem + (n - tn * BT) * kXtStageRow + (i - tm * BT) * 2) = pack4_bf16(v);
           } else {
             const size_t ot = (size_t)n * sp + i;
-            if (P == kF32) st_stream((f32x4*)((float*)XTn + ot), (f32x4){v[0], v[1], v[2], v[3]});
-            else st_stream((uint2*)((uint16_t*)XTn + ot), pack4_bf16(v));
+            if (P == kF32) st_hint<kStream>((f32x4*)((float*)XTn + ot), (f32x4){v[0], v[1], v[2], v[3]});
+            else st_hint<kStream>((uint2*)((uint16_t*)XTn + ot), pack4_bf16(v));
           }
         } else if (stage_out) {
           // tile-local (row, col) in the caller's layout: (i, n), or (n, i) when transposed
@@ -1269,8 +1281,8 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
           for (int r = 0; r < 4; ++r) {
             if (i + r < d.s) {
               const size_t o = d.trans ? (size_t)n * d.ldo + (i + r) : (size_t)(i + r) * d.ldo + n;
-              if (d.out_bf16) st_stream((uint16_t*)d.Out + o, f2bf(v[r]));
-              else st_stream((float*)d.Out + o, v[r]);
+              if (d.out_bf16) st_hint<kStream>((uint16_t*)d.Out + o, f2bf(v[r]));
+              else st_hint<kStream>((float*)d.Out + o, v[r]);
             }
           }
         }
@@ -1284,7 +1296,7 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
     uint16_t* xt = (uint16_t*)XTn + (size_t)tn * BT * sp + (size_t)tm * BT;
     for (int ch = threadIdx.x; ch < 256 * 32; ch += W::NT) {
       const int r = ch >> 5, cc = ch & 31;
-      st_stream((u32x4*)(xt + (size_t)r * sp + cc * 8), *(const u32x4*)(smem + r * kXtStageRow + cc * 16));
+      st_hint<kStream>((u32x4*)(xt + (size_t)r * sp + cc * 8), *(const u32x4*)(smem + r * kXtStageRow + cc * 16));
     }
     // (the next tile's prologue starts with a barrier before it refills the ring)
   }
@@ -1301,9 +1313,9 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
       const char* src = smem + r * kXtStageRow + c8 * 2;
       uint16_t* dst = out + (size_t)gr * d.ldo + gc;
       if (d.o_vec && gc + 8 <= cols) {
-        st_stream((u32x4*)dst, *(const u32x4*)src);
+        st_hint<kStream>((u32x4*)dst, *(const u32x4*)src);
       } else {
-        for (int e = 0; e < 8 && gc + e < cols; ++e) st_stream(dst + e, ((const uint16_t*)src)[e]);
+        for (int e = 0; e < 8 && gc + e < cols; ++e) st_hint<kStream>(dst + e, ((const uint16_t*)src)[e]);
       }
     }
   }
