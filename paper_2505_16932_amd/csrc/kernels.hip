@@ -160,11 +160,17 @@ __device__ __forceinline__ void store_x_chunk(const MatDesc& d, size_t o, const 
   store8_f32<P>(d.Xf + o, v);
   if (P != kF32) store8_bf16((uint16_t*)d.Xb + o, v);
 }
-// X^T row chunk (operand of B X)
+// Element (n, i) of the bf16 X^T (Lp x sp), k-blocked: the k = i axis in blocks
+// of 32, each block Lp rows of 64 bytes.  The update's operand stage is then one
+// contiguous 16-KB block, and the epilogue's transposed stores fill whole rows.
+__device__ __forceinline__ size_t xt_blk(int n, int i, size_t Lp) {
+  return ((size_t)(i >> 5) * Lp + n) * 32 + (i & 31);
+}
+// X^T chunk (operand of B X): row n, columns i..i+7 (fp32 path: row-major)
 template <int P>
-__device__ __forceinline__ void store_xt_chunk(const MatDesc& d, size_t o, const float (&v)[8]) {
-  if (P == kF32) store8_f32<P>((float*)d.XT0 + o, v);
-  else store8_bf16((uint16_t*)d.XT0 + o, v);
+__device__ __forceinline__ void store_xt_chunk(const MatDesc& d, int n, int i, const float (&v)[8]) {
+  if (P == kF32) store8_f32<P>((float*)d.XT0 + (size_t)n * d.sp + i, v);
+  else store8_bf16((uint16_t*)d.XT0 + xt_blk(n, i, d.Lp), v);
 }
 
 template <int P>
@@ -206,7 +212,7 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(KArgs args) {
           amax = fmaxf(amax, fabsf(v[j][e]));
         }
         if (!d.trans) store_x_chunk<P>(d, (size_t)(i0 + r) * d.Lp + k0 + cc, v[j]);
-        else store_xt_chunk<P>(d, (size_t)(k0 + r) * d.sp + i0 + cc, v[j]);
+        else store_xt_chunk<P>(d, k0 + r, i0 + cc, v[j]);
       }
       __syncthreads();
 #pragma unroll
@@ -215,7 +221,7 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(KArgs args) {
         float w[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) w[e] = tile[cc + e][q];
-        if (!d.trans) store_xt_chunk<P>(d, (size_t)(k0 + q) * d.sp + i0 + cc, w);
+        if (!d.trans) store_xt_chunk<P>(d, k0 + q, i0 + cc, w);
         else store_x_chunk<P>(d, (size_t)(i0 + q) * d.Lp + k0 + cc, w);
       }
     }
@@ -471,19 +477,26 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("" ::: "memory");
 }
 
+// P is row-major (row stride ld); Q has row stride ldQ and kbQ elements between
+// consecutive 32-deep k blocks (row-major: ldQ = ld, kbQ = 32; the k-blocked
+// X^T: ldQ = 32, kbQ = 32 * rows)
 template <int BT>
 __device__ __forceinline__ void dl_issue_stage(const PE_GLOBAL uint16_t* P, const PE_GLOBAL uint16_t* Q,
-                                               int64_t ld, int kofs, char* slot, int wave, int lane) {
+                                               int64_t ld, int64_t ldQ, int64_t kbQ, int kofs, char* slot,
+                                               int wave, int lane) {
   typedef DlCfg<BT> C;
+  static_assert(C::BK == 32, "one k block per stage");
 #pragma unroll
   for (int op = 0; op < 2; ++op) {
     const PE_GLOBAL uint16_t* base = op == 0 ? P : Q;
+    const int64_t rs = op == 0 ? ld : ldQ;
+    const int64_t kb = op == 0 ? 32 : kbQ;
 #pragma unroll
     for (int j = 0; j < C::IPW; ++j) {
       const int blk = wave * C::IPW + j;            // 1-KB block = 16 rows
       const int row = blk * 16 + (lane >> 2);
       const int lc = dl_swz(row, lane & 3);          // logical chunk this lane fetches
-      const PE_GLOBAL uint16_t* g = base + (size_t)row * ld + kofs + lc * 8;
+      const PE_GLOBAL uint16_t* g = base + (size_t)row * rs + (size_t)(kofs >> 5) * kb + lc * 8;
       __builtin_amdgcn_global_load_lds((const void*)g,
                                        (__attribute__((address_space(3))) void*)(slot + op * C::OPB + blk * 1024),
                                        16, 0, 0);
@@ -557,18 +570,20 @@ __device__ __forceinline__ void dl_mfma32(const Frags32& f, A (&acc)[4][2]) {
                                                             __builtin_bit_cast(bf16x8, f.b[fn]), acc[fm][fn], 0, 0, 0);
 }
 
-// acc += P[rp0:+BT, k0:k1] * Q[rq0:+BT, k0:k1]^T (bf16), (k1 - k0) % 32 == 0
+// acc += P[rp0:+BT, k0:k1] * Q[rq0:+BT, k0:k1]^T (bf16), k0 and k1 multiples of 32;
+// Q's layout as for dl_issue_stage
 template <int BT, typename A, int FN>
 __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
-                                                const uint16_t* __restrict__ Q, int64_t ld, int rp0,
-                                                int rq0, int k0, int k1, char* smem, A (&acc)[4][FN]) {
+                                                const uint16_t* __restrict__ Q, int64_t ld, int64_t ldQ,
+                                                int64_t kbQ, int rp0, int rq0, int k0, int k1, char* smem,
+                                                A (&acc)[4][FN]) {
   typedef DlCfg<BT> C;
   typedef WaveCfg<kBF16, BT> W;
   static_assert(FN == W::FN, "accumulator grid");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / W::WGN, wn = wave % W::WGN;
   const PE_GLOBAL uint16_t* pP = gview(P) + (size_t)rp0 * ld + k0;
-  const PE_GLOBAL uint16_t* pQ = gview(Q) + (size_t)rq0 * ld + k0;
+  const PE_GLOBAL uint16_t* pQ = gview(Q) + (size_t)rq0 * ldQ + (size_t)(k0 >> 5) * kbQ;
   const int nk = (k1 - k0) / C::BK;
   // prologue: stages 0..NS-2 in flight (a stage past the end re-reads the last
   // one, which keeps the count of outstanding loads per iteration fixed)
@@ -576,7 +591,7 @@ __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
 #pragma unroll
   for (int s = 0; s < C::NS - 1; ++s) {
     const int ks = s < nk ? s : nk - 1;
-    dl_issue_stage<BT>(pP, pQ, ld, ks * C::BK, smem + s * C::STB, wave, lane);
+    dl_issue_stage<BT>(pP, pQ, ld, ldQ, kbQ, ks * C::BK, smem + s * C::STB, wave, lane);
   }
   if constexpr (BT == 128) {
     static_assert(W::NW == 4 && FN == 4, "128 tile: 4 waves");
@@ -586,7 +601,7 @@ __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
       lds_barrier();  // everyone's loads of stage kt landed; stage kt-1's slot is free
       {
         const int ks = kt + C::NS - 1 < nk ? kt + C::NS - 1 : nk - 1;
-        dl_issue_stage<BT>(pP, pQ, ld, ks * C::BK, smem + ((kt + C::NS - 1) % C::NS) * C::STB, wave, lane);
+        dl_issue_stage<BT>(pP, pQ, ld, ldQ, kbQ, ks * C::BK, smem + ((kt + C::NS - 1) % C::NS) * C::STB, wave, lane);
       }
       const char* cur = smem + (kt % C::NS) * C::STB;
       dl_mma_stage<BT>(cur, cur + C::OPB, wm, wn, lane, acc);
@@ -627,7 +642,7 @@ __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
       __builtin_amdgcn_sched_barrier(0);
       {
         const int ks = kt + C::NS - 1 < nk ? kt + C::NS - 1 : nk - 1;
-        dl_issue_stage<BT>(pP, pQ, ld, ks * C::BK, smem + ((kt + C::NS - 1) % C::NS) * C::STB, wave, lane);
+        dl_issue_stage<BT>(pP, pQ, ld, ldQ, kbQ, ks * C::BK, smem + ((kt + C::NS - 1) % C::NS) * C::STB, wave, lane);
       }
       const int nx = kt + 1 < nk ? kt + 1 : kt;
       dl_read_frags32(smem + (nx % C::NS) * C::STB, 0, wm, wn, lane, f0);
@@ -1213,11 +1228,6 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
   typedef TileCfg<BT> C;
   typedef WaveCfg<P, BT> W;
   static_assert(FN == W::FN, "accumulator grid");
-  // On the bf16 256 tile the transposed copy goes through LDS: written there
-  // column by column, then stored as whole 512-byte rows of X^T.  Stored
-  // directly, each 128-byte line of X^T would arrive in 16-byte pieces from
-  // different instructions and leave the L2 partly written.
-  constexpr bool kStageXt = !LAST && P != kF32 && BT == 256;
   // the last step stages a bf16 output tile the same way, in the caller's
   // orientation, and stores whole rows (ragged edges element by element)
   const bool stage_out = LAST && P != kF32 && BT == 256 && d.out_bf16;
@@ -1235,7 +1245,7 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
   const size_t Lp = d.Lp, sp = d.sp;
   void* XTn = (args.t & 1) ? d.XT0 : d.XT1;
   float amax = 0.0f;
-  if (kStageXt || stage_out) __syncthreads();  // every wave is done with the operand ring
+  if (stage_out) __syncthreads();  // every wave is done with the operand ring
   FragRow<P, BT> pre[2];
   load_frag_row<P, BT, float, kStream>(d.Xf, Lp, tm * BT, tn * BT, wm, wn, 0, lane, pre[0]);
 #pragma unroll
@@ -1260,12 +1270,11 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
             if (P != kF32) ((uint16_t*)d.Xb)[o] = f2bf(v[r]);
             amax = fmaxf(amax, fabsf(v[r]));
           }
-          if constexpr (kStageXt) {
-            *(uint2*)(smem + (n - tn * BT) * kXtStageRow + (i - tm * BT) * 2) = pack4_bf16(v);
+          if constexpr (P == kF32) {
+            st_hint<kStream>((f32x4*)((float*)XTn + (size_t)n * sp + i), (f32x4){v[0], v[1], v[2], v[3]});
           } else {
-            const size_t ot = (size_t)n * sp + i;
-            if (P == kF32) st_hint<kStream>((f32x4*)((float*)XTn + ot), (f32x4){v[0], v[1], v[2], v[3]});
-            else st_hint<kStream>((uint2*)((uint16_t*)XTn + ot), pack4_bf16(v));
+            // k-blocked X^T: the four g rows of a fragment fill 32 whole 64-byte rows
+            *(uint2*)((uint16_t*)XTn + xt_blk(n, i, Lp)) = pack4_bf16(v);
           }
         } else if (stage_out) {
           // tile-local (row, col) in the caller's layout: (i, n), or (n, i) when transposed
@@ -1290,16 +1299,6 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
     }
   }
   if (!LAST && args.fp8_next) wave_amax_atomic(amax, d.scal + kScAmaxX + args.t + 1);
-  if constexpr (kStageXt) {
-    __syncthreads();
-    // 256 rows x 32 chunks of 16 bytes; consecutive threads take consecutive chunks of a row
-    uint16_t* xt = (uint16_t*)XTn + (size_t)tn * BT * sp + (size_t)tm * BT;
-    for (int ch = threadIdx.x; ch < 256 * 32; ch += W::NT) {
-      const int r = ch >> 5, cc = ch & 31;
-      st_hint<kStream>((u32x4*)(xt + (size_t)r * sp + cc * 8), *(const u32x4*)(smem + r * kXtStageRow + cc * 16));
-    }
-    // (the next tile's prologue starts with a barrier before it refills the ring)
-  }
   if (stage_out) {
     __syncthreads();
     // staged rows are output rows: i (or n when transposed) from the tile's first row
@@ -1329,13 +1328,15 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
   typedef WaveCfg<P, BT> W;
   typedef typename AccT<C::ACC>::type Acc;
   constexpr int BK = P == kFP8 ? Fp8Cfg<BT>::KQ : (P == kBF16 ? DlCfg<BT>::BK : OpT<T>::kBK);
-  constexpr bool DL = P == kBF16 || (P == kFP8 && BT == 256);  // direct-to-LDS operand ring
+  constexpr bool UPD = KIND == KIND_UPD || KIND == KIND_UPD_LAST;
+  // direct-to-LDS operand ring (the FP8 instantiations run their updates in bf16)
+  constexpr bool DL = P == kBF16 || (P == kFP8 && (BT == 256 || UPD));
   constexpr int LDSB0 = DL ? DlCfg<BT>::LDS : (P == kFP8 ? Fp8Cfg<BT>::LDS : C::LDS);
-  // the 256 tile stages transposed bf16 tiles (the update's X^T, a SYRK
-  // tile's mirror) in the same buffer
+  // the bf16 256 tile stages a SYRK tile's mirror, or the last step's output
+  // tile, in the same buffer
   constexpr bool kStageMirror = P != kF32 && BT == 256;
-  constexpr int LDSB = (BT == 256 && (P != kF32 || KIND == KIND_UPD || KIND == KIND_UPD_LAST) &&
-                        LDSB0 < kXtStageBytes) ? kXtStageBytes : LDSB0;
+  constexpr int LDSB = (BT == 256 && P != kF32 && KIND != KIND_UPD && LDSB0 < kXtStageBytes)
+                           ? kXtStageBytes : LDSB0;
   __shared__ __attribute__((aligned(16))) char smem[LDSB];
   for (int slot = blockIdx.x; slot < args.total; slot += gridDim.x) {
     const int item = xcd_item(slot, args.total);
@@ -1354,8 +1355,10 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
       const T* Bop = (const T*)d.Bs;
       const T* XTc = (const T*)((args.t & 1) ? d.XT1 : d.XT0);
       // (the update always runs in bf16; the FP8 instantiation shares the bf16 loop)
+      // X^T is k-blocked on the bf16 paths: rows of 32 k, one block of Lp rows per 32 k
       if constexpr (DL)
-        gemm_nt_tile_dl<BT>((const uint16_t*)Bop, (const uint16_t*)XTc, d.sp, tm * BT, tn * BT, 0, d.sp, smem, acc);
+        gemm_nt_tile_dl<BT>((const uint16_t*)Bop, (const uint16_t*)XTc, d.sp, 32, (int64_t)32 * d.Lp,
+                            tm * BT, tn * BT, 0, d.sp, smem, acc);
       else
         gemm_nt_tile<T, BT>(Bop, XTc, d.sp, tm * BT, tn * BT, 0, d.sp, smem, acc);
       epi_update<P, BT, KIND == KIND_UPD_LAST>(args, d, tm, tn, acc, smem);
@@ -1388,7 +1391,8 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
         }
       } else if constexpr (P == kBF16) {
         if (k1 > k0)
-          gemm_nt_tile_dl<BT>((const uint16_t*)Op, (const uint16_t*)Op, K, ti * BT, tj * BT, k0, k1, smem, acc);
+          gemm_nt_tile_dl<BT>((const uint16_t*)Op, (const uint16_t*)Op, K, K, 32, ti * BT, tj * BT, k0, k1,
+                              smem, acc);
       } else {
         if (k1 > k0) gemm_nt_tile<T, BT>(Op, Op, K, ti * BT, tj * BT, k0, k1, smem, acc);
       }

@@ -9,7 +9,8 @@
 // bounds checks; only the input read and the final store see m, n.
 //   Xf      sp x Lp  fp32   master iterate (row-major)
 //   Xb      sp x Lp  bf16   operand copy of X for the Gram product (bf16/fp8 paths)
-//   XT[2]   Lp x sp  bf16 or fp32   X^T operand for B X (ping-pong across steps)
+//   XT[2]   Lp x sp  bf16 or fp32   X^T operand for B X (ping-pong across steps); the
+//                           bf16 copy is k-blocked: element (n, i) at ((i/32) Lp + n) 32 + i%32
 //   Af      sp x sp  fp32   A = X X^T (fp32 path only)
 //   As      sp x sp  bf16   A in bf16 on the bf16/fp8 paths, read by A^2 and by
 //                           the bA term of B (fp32 path: Af itself)
