@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "pe_device.h"
 
 namespace pe {
@@ -1527,37 +1529,92 @@ hipError_t launch_put(const PutChunk& c, hipStream_t st) {
   return hipGetLastError();
 }
 
-static int grid_for(int total, int cap) { return total < cap ? (total > 0 ? total : 1) : cap; }
+// Blocks of a kernel that fit on the device at once (occupancy calculator x CU
+// count), cached per device and kernel; 0 if the runtime cannot say.  A
+// grid-stride kernel launched with more blocks than this runs the surplus in
+// a second round that leaves most of the device idle.
+static int resident_blocks(const void* kernel, int threads) {
+  constexpr int kDev = 16, kSlots = 64;
+  static const void* keys[kDev][kSlots];
+  static int vals[kDev][kSlots];
+  static std::mutex mu;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDev) return 0;
+  std::lock_guard<std::mutex> lock(mu);
+  for (int i = 0; i < kSlots; ++i) {
+    if (keys[dev][i] == kernel) return vals[dev][i];
+    if (keys[dev][i]) continue;
+    int ncu = 0, per = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess) {
+      (void)hipGetLastError();  // a failed query must not read as a failed launch
+      return 0;
+    }
+    keys[dev][i] = kernel;
+    vals[dev][i] = per * ncu;
+    return vals[dev][i];
+  }
+  return 0;
+}
+
+template <typename K>
+static int grid_for(int total, int cap, K kernel, int threads) {
+  const int res = resident_blocks(reinterpret_cast<const void*>(kernel), threads);
+  if (res > 0 && res < cap) cap = res;
+  return total < cap ? (total > 0 ? total : 1) : cap;
+}
+
+template <int P, int BT>
+static void warm_t() {
+  constexpr int nt = WaveCfg<P, BT>::NT;
+  resident_blocks(reinterpret_cast<const void*>(gemm_kernel<P, KIND_GRAM, BT>), nt);
+  resident_blocks(reinterpret_cast<const void*>(gemm_kernel<P, KIND_A2, BT>), nt);
+  resident_blocks(reinterpret_cast<const void*>(gemm_kernel<P, KIND_UPD, BT>), nt);
+  resident_blocks(reinterpret_cast<const void*>(gemm_kernel<P, KIND_UPD_LAST, BT>), nt);
+  resident_blocks(reinterpret_cast<const void*>(splitk_reduce_kernel<P, KIND_GRAM, BT>), nt);
+  resident_blocks(reinterpret_cast<const void*>(splitk_reduce_kernel<P, KIND_A2, BT>), nt);
+}
+
+// Fills the resident-block cache of the current device, so that launches
+// recorded into a graph later make no runtime queries.
+void warm_launch_grids() {
+  resident_blocks(reinterpret_cast<const void*>(prep_kernel<kF32>), kThreads);
+  resident_blocks(reinterpret_cast<const void*>(prep_kernel<kBF16>), kThreads);
+  resident_blocks(reinterpret_cast<const void*>(quant_kernel<KIND_GRAM>), kThreads);
+  resident_blocks(reinterpret_cast<const void*>(quant_kernel<KIND_A2>), kThreads);
+  warm_t<kF32, 128>();
+  warm_t<kF32, 256>();
+  warm_t<kBF16, 128>();
+  warm_t<kBF16, 256>();
+  warm_t<kFP8, 128>();
+  warm_t<kFP8, 256>();
+}
 
 hipError_t launch_prep(int prec, const KArgs& a, int grid_cap, hipStream_t st) {
-  const int g = grid_for(a.total, grid_cap);
-  if (prec == kF32) hipLaunchKernelGGL(prep_kernel<kF32>, dim3(g), dim3(kThreads), 0, st, a);
-  else hipLaunchKernelGGL(prep_kernel<kBF16>, dim3(g), dim3(kThreads), 0, st, a);
+  auto k = prec == kF32 ? prep_kernel<kF32> : prep_kernel<kBF16>;
+  hipLaunchKernelGGL(k, dim3(grid_for(a.total, grid_cap, k, kThreads)), dim3(kThreads), 0, st, a);
   return hipGetLastError();
 }
 
 template <int P, int BT>
-static void launch_gemm_t(int kind, const KArgs& a, int g, hipStream_t st) {
-  if (kind == KIND_GRAM)
-    hipLaunchKernelGGL((gemm_kernel<P, KIND_GRAM, BT>), dim3(g), dim3(WaveCfg<P, BT>::NT), 0, st, a);
-  else if (kind == KIND_A2)
-    hipLaunchKernelGGL((gemm_kernel<P, KIND_A2, BT>), dim3(g), dim3(WaveCfg<P, BT>::NT), 0, st, a);
-  else if (!a.last)
-    hipLaunchKernelGGL((gemm_kernel<P, KIND_UPD, BT>), dim3(g), dim3(WaveCfg<P, BT>::NT), 0, st, a);
-  else
-    hipLaunchKernelGGL((gemm_kernel<P, KIND_UPD_LAST, BT>), dim3(g), dim3(WaveCfg<P, BT>::NT), 0, st, a);
+static void launch_gemm_t(int kind, const KArgs& a, int cap, hipStream_t st) {
+  auto k = kind == KIND_GRAM ? gemm_kernel<P, KIND_GRAM, BT>
+         : kind == KIND_A2   ? gemm_kernel<P, KIND_A2, BT>
+         : !a.last           ? gemm_kernel<P, KIND_UPD, BT>
+                             : gemm_kernel<P, KIND_UPD_LAST, BT>;
+  constexpr int nt = WaveCfg<P, BT>::NT;
+  hipLaunchKernelGGL(k, dim3(grid_for(a.total, cap, k, nt)), dim3(nt), 0, st, a);
 }
 
 template <int P, int BT>
-static void launch_reduce_t(int kind, const KArgs& a, int g, hipStream_t st) {
-  if (kind == KIND_GRAM)
-    hipLaunchKernelGGL((splitk_reduce_kernel<P, KIND_GRAM, BT>), dim3(g), dim3(WaveCfg<P, BT>::NT), 0, st, a);
-  else
-    hipLaunchKernelGGL((splitk_reduce_kernel<P, KIND_A2, BT>), dim3(g), dim3(WaveCfg<P, BT>::NT), 0, st, a);
+static void launch_reduce_t(int kind, const KArgs& a, int cap, hipStream_t st) {
+  auto k = kind == KIND_GRAM ? splitk_reduce_kernel<P, KIND_GRAM, BT> : splitk_reduce_kernel<P, KIND_A2, BT>;
+  constexpr int nt = WaveCfg<P, BT>::NT;
+  hipLaunchKernelGGL(k, dim3(grid_for(a.total, cap, k, nt)), dim3(nt), 0, st, a);
 }
 
 hipError_t launch_gemm(int prec, int bt, int kind, const KArgs& a, int grid_cap, hipStream_t st) {
-  const int g = grid_for(a.total, grid_cap);
+  const int g = grid_cap;
   if (prec == kFP8 && kind != KIND_UPD) {
     if (bt == 256) launch_gemm_t<kFP8, 256>(kind, a, g, st);
     else launch_gemm_t<kFP8, 128>(kind, a, g, st);
@@ -1572,14 +1629,13 @@ hipError_t launch_gemm(int prec, int bt, int kind, const KArgs& a, int grid_cap,
 }
 
 hipError_t launch_quant(int kind, const KArgs& a, int grid_cap, hipStream_t st) {
-  const int g = grid_for(a.total, grid_cap);
-  if (kind == KIND_GRAM) hipLaunchKernelGGL(quant_kernel<KIND_GRAM>, dim3(g), dim3(kThreads), 0, st, a);
-  else hipLaunchKernelGGL(quant_kernel<KIND_A2>, dim3(g), dim3(kThreads), 0, st, a);
+  auto k = kind == KIND_GRAM ? quant_kernel<KIND_GRAM> : quant_kernel<KIND_A2>;
+  hipLaunchKernelGGL(k, dim3(grid_for(a.total, grid_cap, k, kThreads)), dim3(kThreads), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce(int prec, int bt, int kind, const KArgs& a, int grid_cap, hipStream_t st) {
-  const int g = grid_for(a.total, grid_cap);
+  const int g = grid_cap;
   if (prec == kFP8) {
     if (bt == 256) launch_reduce_t<kFP8, 256>(kind, a, g, st);
     else launch_reduce_t<kFP8, 128>(kind, a, g, st);

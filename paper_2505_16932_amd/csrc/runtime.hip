@@ -36,6 +36,7 @@ hipError_t launch_mlp_grad(const float* params, const float* feats, const int32_
 hipError_t launch_quantize(const void* x, int x_bf16, uint8_t* q, int64_t n, float scale,
                            hipStream_t st);
 hipError_t launch_prep(int prec, const KArgs& a, int grid_cap, hipStream_t st);
+void warm_launch_grids();
 hipError_t launch_gemm(int prec, int bt, int kind, const KArgs& a, int grid_cap, hipStream_t st);
 hipError_t launch_reduce(int prec, int bt, int kind, const KArgs& a, int grid_cap, hipStream_t st);
 }  // namespace pe
@@ -534,6 +535,7 @@ pe_status plan_init(pe_plan* p, int count, const pe_matrix* mats, const pe_opts*
   if (sizing.totals[PH_PREP] == 0) return PE_OK;  // nothing but empty matrices
   if (!ws || ((uintptr_t)ws & 255) || ws_bytes < sizing.bytes) return PE_EWORKSPACE;
   build_layout(count, mats, o, (char*)ws, &p->L);
+  warm_launch_grids();
   return upload(p, (char*)ws, st);
 }
 
