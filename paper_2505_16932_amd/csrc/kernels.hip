@@ -2,15 +2,18 @@
 // Appendix A.1 listing: X_0 = G / (1.01 ||G||_F + 1e-7); per step
 // A = X X^T, B = b A + c A^2, X = a X + B X).
 //
-// Three kernel families, each launched once per phase over the tiles of every
-// matrix of a call ("grouped" launches; a single matrix is a group of one):
+// Kernels, each launched once per phase over the items of every matrix of a
+// call ("grouped" launches; a single matrix is a group of one), each walking
+// its items in a grid-stride loop:
 //   prep_kernel   one HBM pass over G: orientation, sum of squares (FP64 per
 //                 lane, fixed-order cross-block reduction => deterministic),
 //                 max |G|, and the unscaled FP32 / bf16 / transposed copies of
 //                 X_0; the scale sigma is folded into step 1's epilogues
 //                 (A_1 = sigma^2 G G^T, X_1 = sigma (a G + B_1 G)).
-//   gemm_kernel   128x128 block tiles, 4 wave64 in 2x2, bf16 16x16x32 or
-//                 fp32 16x16x4 MFMA, FP32 accumulation, LDS double buffer.
+//   gemm_kernel   persistent blocks over block tiles of 128 (4 waves, 16x16x32
+//                 MFMA, two blocks per CU) or 256 (8 waves in 2 x 4, 32x32x16
+//                 MFMA, one block per CU); bf16 operands go from HBM straight
+//                 into a four-stage LDS ring, FP32 accumulation.
 //                 KIND_GRAM:  A = X X^T, upper-triangle tiles only, mirrored
 //                             store (SYRK);
 //                 KIND_A2:    B = b A + c A A^T (A symmetric, so A^2 = A A^T is
@@ -19,6 +22,9 @@
 //                             operand; writes the FP32 master, the bf16 copy
 //                             and the next X^T, or the caller's output on the
 //                             last step.
+//                 In the e4m3 steps the Gram-side products read e4m3 copies
+//                 (quant_kernel) on the 256 tile, or convert bf16 operands
+//                 while staging them on the 128 tile.
 //                 Split-K for the Gram-side products writes partial tiles;
 //                 splitk_reduce_kernel sums them in split order (deterministic)
 //                 and runs the same epilogue.
@@ -284,14 +290,15 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(KArgs args) {
 }
 
 // ------------------------------------------------------------- GEMM core
-// Block tile BT x BT (BT = 128 or 256), 4 wave64 in a 2 x 2 grid, each wave a
-// (BT/2) x (BT/2) tile of 4 x 4 MFMA fragments of F x F, F = BT/8:
+// Block tile BT x BT (BT = 128 or 256) of MFMA fragments F x F, F = BT/8:
 //   F = 16: v_mfma_f32_16x16x32_bf16 / v_mfma_f32_16x16x4_f32
 //   F = 32: v_mfma_f32_32x32x16_bf16 / v_mfma_f32_32x32x2_f32
-// One LDS stage holds 128 bytes of k per row (64 bf16 or 32 fp32) plus a
-// 16-byte pad (bank spread), for both operands; two stages are double-buffered.
-// A lane reads its fragment as one 16-byte chunk: rows lane % F, k-chunk
-// lane / F within a sub-step of F == 16 ? 64 : 32 bytes.
+// (the wave grid per path is WaveCfg below).  The register-staged FP32 loop
+// (gemm_nt_tile, 4 waves in 2 x 2, each a (BT/2) x (BT/2) tile of 4 x 4
+// fragments) keeps 128 bytes of k per LDS row (32 fp32) plus a 16-byte pad
+// (bank spread), for both operands, in two double-buffered stages; a lane
+// reads its fragment as one 16-byte chunk: rows lane % F, k-chunk lane / F
+// within a sub-step of F == 16 ? 64 : 32 bytes.
 constexpr int kRowBytes = 144;
 
 template <int BT>
@@ -329,13 +336,11 @@ struct WaveCfg {
   static constexpr int WTN = FN * F;
 };
 
+// The FP32 path stages its operands through registers (the bf16 and e4m3
+// paths use the direct-to-LDS ring below): 32 fp32 of k per LDS stage, four
+// per 16-byte chunk.
 template <typename T>
 struct OpT;
-template <>
-struct OpT<uint16_t> {  // bf16
-  static constexpr int kVec = 8;   // elements per 16-byte chunk
-  static constexpr int kBK = 64;   // k per LDS stage (128 bytes)
-};
 template <>
 struct OpT<float> {
   static constexpr int kVec = 4;
@@ -360,25 +365,14 @@ __device__ __forceinline__ void mma_stage(const char* sA, const char* sB, int wm
     for (int fm = 0; fm < 4; ++fm) {
 #pragma unroll
       for (int fn = 0; fn < 4; ++fn) {
-        if constexpr (sizeof(T) == 2) {
-          if constexpr (F == 16)
-            acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                __builtin_bit_cast(bf16x8, fa[fm]), __builtin_bit_cast(bf16x8, fb[fn]), acc[fm][fn],
-                0, 0, 0);
-          else
-            acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, fa[fm]), __builtin_bit_cast(bf16x8, fb[fn]), acc[fm][fn],
-                0, 0, 0);
-        } else {
-          const f32x4 a4 = __builtin_bit_cast(f32x4, fa[fm]);
-          const f32x4 b4 = __builtin_bit_cast(f32x4, fb[fn]);
+        const f32x4 a4 = __builtin_bit_cast(f32x4, fa[fm]);
+        const f32x4 b4 = __builtin_bit_cast(f32x4, fb[fn]);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            if constexpr (F == 16)
-              acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[e], b4[e], acc[fm][fn], 0, 0, 0);
-            else
-              acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[e], b4[e], acc[fm][fn], 0, 0, 0);
-          }
+        for (int e = 0; e < 4; ++e) {
+          if constexpr (F == 16)
+            acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[e], b4[e], acc[fm][fn], 0, 0, 0);
+          else
+            acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[e], b4[e], acc[fm][fn], 0, 0, 0);
         }
       }
     }
@@ -390,6 +384,7 @@ template <typename T, int BT, typename A>
 __device__ __forceinline__ void gemm_nt_tile(const T* __restrict__ P, const T* __restrict__ Q,
                                              int64_t ld, int rp0, int rq0, int k0, int k1,
                                              char* smem, A (&acc)[4][4]) {
+  static_assert(sizeof(T) == 4, "register-staged tiles serve the FP32 path");
   typedef TileCfg<BT> C;
   constexpr int BK = OpT<T>::kBK, VEC = OpT<T>::kVec, CPT = C::CPT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1329,7 +1324,7 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
   typedef TileCfg<BT> C;
   typedef WaveCfg<P, BT> W;
   typedef typename AccT<C::ACC>::type Acc;
-  constexpr int BK = P == kFP8 ? Fp8Cfg<BT>::KQ : (P == kBF16 ? DlCfg<BT>::BK : OpT<T>::kBK);
+  constexpr int BK = P == kFP8 ? Fp8Cfg<BT>::KQ : (P == kBF16 ? DlCfg<BT>::BK : OpT<float>::kBK);
   constexpr bool UPD = KIND == KIND_UPD || KIND == KIND_UPD_LAST;
   // direct-to-LDS operand ring (the FP8 instantiations run their updates in bf16)
   constexpr bool DL = P == kBF16 || (P == kFP8 && (BT == 256 || UPD));
