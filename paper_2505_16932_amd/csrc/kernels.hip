@@ -46,6 +46,7 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef short i16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));
 
 // Streaming (non-temporal) stores and loads, for data that a launch touches
 // once: outputs that only later launches read should not displace from the L2
@@ -1089,9 +1090,13 @@ __device__ __forceinline__ void load_frag_row_sym(const uint16_t* __restrict__ A
 constexpr int kXtStageRow = 528;
 constexpr int kXtStageBytes = 256 * kXtStageRow;
 
-// STAGE (bf16 operands of the 256 tile): an off-diagonal tile's mirror is
-// written to LDS column by column and stored as whole rows; stored directly,
-// it would leave the L2 in 8-byte pieces from 64 different rows per instruction.
+// STAGE (bf16 operands of the 256 tile): the tile goes to LDS transposed,
+// column by column, and leaves it as whole rows twice: the staged rows are the
+// mirror tile's rows, and the tile's own rows are gathered from the staged
+// columns with transposing LDS reads (ds_read_b64_tr_b16: within each 16
+// lanes, lane 4a+j receives element j of the 8-byte rows addressed by lanes a,
+// a+4, a+8, a+12).  Stored directly, the mirror would leave the L2 in 8-byte
+// pieces of 64 rows per instruction and the tile in 2-byte ones.
 template <int P, int BT, bool STAGE, typename A, int FN>
 __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, int kind, int ti,
                                          int tj, float deq, const A (&acc)[4][FN], double* red,
@@ -1118,7 +1123,7 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
   typedef typename std::conditional<P == kF32, float, uint16_t>::type AT;
   const AT* Asrc = P == kF32 ? (const AT*)d.Af : (const AT*)d.As;
   static_assert(!STAGE || (P != kF32 && BT == 256), "mirror staging: bf16 tiles of 256");
-  const bool stage = STAGE && ti != tj && !(kind == KIND_A2 && args.raw_a2);
+  const bool stage = STAGE && !(kind == KIND_A2 && args.raw_a2);
   if (stage) __syncthreads();  // every wave is done with the operand ring
   FragRow<P, BT> pre[2];
   auto load_a = [&](int fm, FragRow<P, BT>& f) {
@@ -1144,7 +1149,7 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
           if (kind == KIND_GRAM) {
             v[r] = alpha * x;
             if (P == kF32) d.Af[o] = v[r];
-            else ((uint16_t*)d.As)[o] = f2bf(v[r]);
+            else if constexpr (!STAGE) ((uint16_t*)d.As)[o] = f2bf(v[r]);
             amax = fmaxf(amax, fabsf(v[r]));
           } else if (args.raw_a2) {
             // learned path, step 1: keep A^2 and accumulate tr(A^k) partials;
@@ -1162,7 +1167,7 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
             // same operation order as the learned path's combine kernel
             v[r] = __builtin_fmaf(calpha, x, b * cur.x[fn][g][r]);
             if (P == kF32) ((float*)d.Bs)[o] = v[r];
-            else ((uint16_t*)d.Bs)[o] = f2bf(v[r]);
+            else if constexpr (!STAGE) ((uint16_t*)d.Bs)[o] = f2bf(v[r]);
           }
         }
         if (ti != tj && kind == KIND_A2 && args.raw_a2) {
@@ -1183,13 +1188,33 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
       }
     }
   }
-  if (stage) {
+  if constexpr (STAGE) if (stage) {
     __syncthreads();
-    // mirror rows j = tj*BT + r, columns ti*BT .. +255: 256 rows x 32 chunks of 16 bytes
-    uint16_t* mir = (uint16_t*)(kind == KIND_GRAM ? d.As : d.Bs) + (size_t)tj * BT * sp + (size_t)ti * BT;
-    for (int ch = threadIdx.x; ch < 256 * 32; ch += W::NT) {
-      const int r = ch >> 5, cc = ch & 31;
-      *(u32x4*)(mir + (size_t)r * sp + cc * 8) = *(const u32x4*)(smem + r * kXtStageRow + cc * 16);
+    uint16_t* dst = (uint16_t*)(kind == KIND_GRAM ? d.As : d.Bs);
+    if (ti != tj) {
+      // mirror rows j = tj*BT + r, columns ti*BT .. +255: 256 rows x 32 chunks of 16 bytes
+      uint16_t* mir = dst + (size_t)tj * BT * sp + (size_t)ti * BT;
+      for (int ch = threadIdx.x; ch < 256 * 32; ch += W::NT) {
+        const int r = ch >> 5, cc = ch & 31;
+        *(u32x4*)(mir + (size_t)r * sp + cc * 8) = *(const u32x4*)(smem + r * kXtStageRow + cc * 16);
+      }
+    }
+    // the tile's own rows: each 16 lanes take tile columns 8 jb .. 8 jb + 7
+    // (staged rows) of 16 tile rows (staged columns) per step; lane s then
+    // holds row 16 ib + s, eight columns, as one 16-byte store
+    static_assert(W::NT / 16 == 32, "one 16-lane group per 8 columns");
+    const int jb = threadIdx.x >> 4, s = threadIdx.x & 15;
+    uint16_t* own = dst + (size_t)ti * BT * sp + (size_t)tj * BT + 8 * jb;
+#pragma unroll 4
+    for (int ib = 0; ib < 16; ++ib) {
+      u32x2 h[2];
+#pragma unroll
+      for (int rd = 0; rd < 2; ++rd) {
+        const char* p = smem + (8 * jb + 4 * rd + (s >> 2)) * kXtStageRow + (16 * ib + 4 * (s & 3)) * 2;
+        h[rd] = __builtin_bit_cast(u32x2, __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+                                              (__attribute__((address_space(3))) i16x4*)(p)));
+      }
+      *(u32x4*)(own + (size_t)(16 * ib + s) * sp) = (u32x4){h[0][0], h[0][1], h[1][0], h[1][1]};
     }
     // (the next tile's prologue starts with a barrier before it refills the ring)
   }
