@@ -18,6 +18,8 @@ Metric: algorithmic TFLOP/s = sum over matrices and steps of (3 s^2 L + s^3)
 (s = min(m,n), L = max(m,n): Gram s^2 L, A^2 s^3 on the symmetric half, B X
 2 s^2 L) divided by the wall time of the step.  pct_mfma_peak weights each
 product by the dense peak of its precision (bf16 2.5, e4m3 5.0 PFLOP/s).
+dense_equivalent_tflops counts the products as plain GEMMs instead
+(4 s^2 L + 2 s^3: full Gram and A^2, the paper's multiply-add count x 2).
 The comparison path runs the same matrices one plain bf16 call at a time.
 
 Prints ONE JSON line (rank 0, N = 1).
@@ -48,6 +50,14 @@ def algo_flops(shapes, T):
     for m, n in shapes:
         s, L = min(m, n), max(m, n)
         tot += 3.0 * s * s * L + float(s) ** 3
+    return tot * T
+
+
+def dense_flops(shapes, T):
+    tot = 0.0
+    for m, n in shapes:
+        s, L = min(m, n), max(m, n)
+        tot += 4.0 * s * s * L + 2.0 * float(s) ** 3
     return tot * T
 
 
@@ -313,6 +323,7 @@ def main():
         "pct_bf16_peak": round(100.0 * tflops / peak, 2),
         "pct_mfma_peak": round(pct_mfma, 2),
         "matrices_per_s": round(len(Gs) / (ms * 1e-3), 2),
+        "dense_equivalent_tflops": round(dense_flops(shapes, T) / (ms * 1e-3) / 1e12, 2),
         "roofline": {"bound": "mfma", "achieved": round(upd_tf, 2), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(upd_tf / peak, 4),
                      "traffic": traffic["gb"] if traffic else None,
