@@ -13,6 +13,7 @@ Workloads:
   wide-layer        one layer of the above (7 matrices), for profiler runs
   gpt-small-batch   12 layers x {768x2304, 768x768, 768x3072, 3072x768} (48), sigma_i = 1/i
   single-4096x1024  one 4096x1024 bf16 matrix, log-uniform spectrum
+  small-256         one 256x256 FP32 matrix, iid N(0,1) (latency-bound: read ms_per_step)
 
 Metric: algorithmic TFLOP/s = sum over matrices and steps of (3 s^2 L + s^3)
 (s = min(m,n), L = max(m,n): Gram s^2 L, A^2 s^3 on the symmetric half, B X
@@ -89,6 +90,12 @@ def make_workload(name, torch, device, inputs="spectral"):
         mats, templates = synth.torch_layer_batch(12, seed=1003, device=device,
                                                   shapes=synth.GPT_SMALL_SHAPES)
         return [m[0] for m in mats], 5, dict(mats=mats, templates=templates)
+    if name == "small-256":
+        import numpy as np
+        G64 = synth.rng(1001).standard_normal((256, 256))
+        U, _, Vt = np.linalg.svd(G64)   # reference polar factor, for the error printout only
+        G = torch.from_numpy(G64.astype("float32")).to(device)
+        return [G], 5, dict(polar=torch.from_numpy(U @ Vt).float().to(device))
     if name == "single-4096x1024":
         S = synth.loguniform(1002)
         G = torch.from_numpy(S.G.astype("float32")).to(torch.bfloat16).to(device)
@@ -98,6 +105,8 @@ def make_workload(name, torch, device, inputs="spectral"):
 
 def polar_factor(meta, idx, torch):
     """U' V^T of matrix idx (known by construction)."""
+    if "polar" in meta:
+        return meta["polar"]
     if "mats" in meta:
         G, perm, signs, j = meta["mats"][idx]
         U, sig, V = meta["templates"][j]
@@ -165,7 +174,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="wide-batch",
-                    choices=["wide-batch", "wide-layer", "gpt-small-batch", "single-4096x1024"])
+                    choices=["wide-batch", "wide-layer", "gpt-small-batch", "single-4096x1024", "small-256"])
     ap.add_argument("--compute", default=None, choices=["bf16", "fp8", "f32"],
                     help="default: fp8 (Gram-side steps 1-3) for wide-batch, bf16 otherwise")
     ap.add_argument("--fp8-steps", type=int, default=None)
