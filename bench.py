@@ -8,8 +8,10 @@ hipGraph).  Inputs are synthetic, seeded, resident in HBM before timing.
 Workloads:
   wide-batch        32-layer 4096-wide model: per layer four 4096x4096 and three
                     4096x14336 bf16 matrices (224), sigma_i = 1/i, Haar singular
-                    vectors, T = 5; the Gram-side products of steps 1-3 in e4m3
-                    with per-tensor scales, everything else bf16    (default)
+                    vectors, T = 5, bf16 MFMA operands with FP32 accumulation
+                    and FP32 master iterate (default); the e4m3 variant (Gram-side
+                    products of steps 1-3 in e4m3) is timed after it and reported
+                    under "fp8_variant"
   wide-layer        one layer of the above (7 matrices), for profiler runs
   gpt-small-batch   12 layers x {768x2304, 768x768, 768x3072, 3072x768} (48), sigma_i = 1/i
   single-4096x1024  one 4096x1024 bf16 matrix, log-uniform spectrum
@@ -22,6 +24,11 @@ product by the dense peak of its precision (bf16 2.5, e4m3 5.0 PFLOP/s).
 dense_equivalent_tflops counts the products as plain GEMMs instead
 (4 s^2 L + 2 s^3: full Gram and A^2, the paper's multiply-add count x 2).
 The comparison path runs the same matrices one plain bf16 call at a time.
+Accuracy: ||X_T - U V^T||_2 for every matrix (U V^T known by construction;
+power iteration on the device), its prediction from the scalar composite on
+the known spectrum (max_i |1 - phi_T(sigma_i / (1.01 ||G||_F))|), and the
+relative Frobenius distance of the GPU result from the FP64 oracle's same
+iteration on the matrix the CPU baseline runs.
 
 Prints ONE JSON line (rank 0, N = 1).
 """
@@ -103,14 +110,20 @@ def make_workload(name, torch, device, inputs="spectral"):
     raise SystemExit(f"unknown workload {name}")
 
 
+def factors(meta, idx):
+    """(U', V) with U' V^T the polar factor of matrix idx (known by construction)."""
+    G, perm, signs, j = meta["mats"][idx]
+    U, sig, V = meta["templates"][j]
+    return U[:, perm] * signs, V
+
+
 def polar_factor(meta, idx, torch):
     """U' V^T of matrix idx (known by construction)."""
     if "polar" in meta:
         return meta["polar"]
     if "mats" in meta:
-        G, perm, signs, j = meta["mats"][idx]
-        U, sig, V = meta["templates"][j]
-        return (U[:, perm] * signs) @ V.T
+        Up, V = factors(meta, idx)
+        return Up @ V.T
     S = meta["synth"]
     return torch.from_numpy(S.polar()).float().cuda()
 
@@ -127,6 +140,79 @@ def spec_norm_gpu(D, torch, iters=60):
         lam = w.norm()
         v = w / lam
     return float(lam.sqrt())
+
+
+def spec_norm_factored(X, Up, V, torch, iters=40):
+    """||X - Up V^T||_2 by power iteration, the difference applied through its
+    factors (no m x n temporary; measurement only)."""
+    X = X.float()
+    g = torch.Generator(device=X.device)
+    g.manual_seed(0)
+    v = torch.randn(X.shape[1], device=X.device, generator=g, dtype=torch.float32)
+    v /= v.norm()
+    for _ in range(iters):
+        y = X @ v - Up @ (V.T @ v)
+        w = X.T @ y - V @ (Up.T @ y)
+        v = w / w.norm()
+    return float((X @ v - Up @ (V.T @ v)).norm())
+
+
+def polar_errors(outs, meta, torch):
+    """||X_T - U V^T||_2 of every matrix of the workload."""
+    errs = []
+    for idx, X in enumerate(outs):
+        if "mats" in meta:
+            Up, V = factors(meta, idx)
+            errs.append(spec_norm_factored(X, Up, V, torch))
+        else:
+            errs.append(spec_norm_gpu(X.float() - polar_factor(meta, idx, torch).float(), torch))
+    return errs
+
+
+def predicted_polar_error(sigma, abc):
+    """max_i |1 - phi_T(sigma_i / (1.01 ||G||_F + 1e-7))| for a known spectrum:
+    the polar error of the exact iteration (the matrix error is the scalar
+    composite's error on the normalised singular values)."""
+    import numpy as np
+    sigma = np.asarray(sigma, dtype=np.float64)
+    x = sigma / (1.01 * np.sqrt(np.sum(sigma ** 2)) + 1e-7)
+    for a, b, c in np.asarray(abc, dtype=np.float64).reshape(-1, 3):
+        y = x * x
+        x = x * (a + y * (b + c * y))
+    return float(np.max(np.abs(1.0 - x)))
+
+
+def err_summary(errs):
+    import numpy as np
+    e = np.asarray(errs)
+    return dict(min=round(float(e.min()), 5), max=round(float(e.max()), 5),
+                mean=round(float(e.mean()), 5))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def time_plan(plan, steps, warmup, stream, torch):
+    for _ in range(warmup):
+        plan.launch(graph=True)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        plan.launch(graph=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    return ev0.elapsed_time(ev1) / steps, wall / steps * 1e3
 
 
 def measured_traffic(workload, compute, tile, fp8_steps):
@@ -151,8 +237,8 @@ def measured_traffic(workload, compute, tile, fp8_steps):
 
 
 def cpu_baseline(G_cpu64, abc, T):
-    """The FP64 oracle on the host cores, on one matrix of the workload."""
-    import numpy as np
+    """The FP64 oracle on the host cores, on one matrix of the workload.
+    Returns the baseline record and the oracle's result."""
     from oracle import iteration as OI
     try:
         from threadpoolctl import threadpool_info
@@ -160,12 +246,18 @@ def cpu_baseline(G_cpu64, abc, T):
     except Exception:
         cores = os.cpu_count()
     t0 = time.perf_counter()
-    OI.polar_express(G_cpu64, abc)
+    ref = OI.polar_express(G_cpu64, abc)
     dt = time.perf_counter() - t0
     m, n = G_cpu64.shape
     fl = algo_flops([(m, n)], T)
     return dict(value=fl / dt / 1e12, unit="TFLOP/s", cores=int(cores), kind="oracle",
-                sample=f"1 of the workload's matrices ({m}x{n}), T={T}, FP64 NumPy, {dt:.1f} s")
+                cpu=cpu_model(),
+                sample=f"1 of the workload's matrices ({m}x{n}), T={T}, FP64 NumPy, {dt:.1f} s"), ref
+
+
+def rel_fro_np(X, ref):
+    import numpy as np
+    return float(np.linalg.norm(X - ref) / np.linalg.norm(ref))
 
 
 def main():
@@ -176,8 +268,10 @@ def main():
     ap.add_argument("--workload", default="wide-batch",
                     choices=["wide-batch", "wide-layer", "gpt-small-batch", "single-4096x1024", "small-256"])
     ap.add_argument("--compute", default=None, choices=["bf16", "fp8", "f32"],
-                    help="default: fp8 (Gram-side steps 1-3) for wide-batch, bf16 otherwise")
+                    help="arithmetic of the timed plan: bf16 (default; f32 for small-256)")
     ap.add_argument("--fp8-steps", type=int, default=None)
+    ap.add_argument("--no-fp8-variant", action="store_true",
+                    help="skip the e4m3 variant timed after the main plan (wide batches)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-error", action="store_true")
@@ -190,7 +284,7 @@ def main():
                          "that scales the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.compute is None:
-        args.compute = "fp8" if args.workload == "wide-batch" else "bf16"
+        args.compute = "f32" if args.workload == "small-256" else "bf16"
     if args.fp8_steps is None:
         args.fp8_steps = 3 if args.compute == "fp8" else 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -224,26 +318,28 @@ def main():
     shapes = [tuple(G.shape) for G in Gs]
     abc = pe.coeffs(1e-3, T).abc
     stream = torch.cuda.current_stream()
+    flops = algo_flops(shapes, T)
+    with_err = not args.no_error and "gaussian" not in meta
+    ref_idx = len(Gs) - 1           # the matrix the CPU oracle runs
+    samples = {}                    # GPU results of that matrix, per variant
+
+    def fp8_flops(steps):
+        fl = 0.0
+        for m, n in shapes:
+            s_, L_ = min(m, n), max(m, n)
+            fl += (float(s_) * s_ * L_ + float(s_) ** 3) * min(steps, T)
+        return fl
+
+    def pct_mfma(ms, steps):
+        f8 = fp8_flops(steps)
+        return 100.0 * ((flops - f8) / (PEAK_BF16_TFLOPS * 1e12) +
+                        f8 / (PEAK_FP8_TFLOPS * 1e12)) / (ms * 1e-3)
 
     plan = pe.Plan(Gs, T=T, abc=abc, compute=args.compute, fp8_steps=args.fp8_steps, tile=args.tile)
-    log(f"[bench] plan ready, workspace {plan.ws_bytes / 2**30:.1f} GiB")
-    for _ in range(args.warmup):
-        plan.launch(graph=True)
-    torch.cuda.synchronize()
-    log("[bench] warmup done")
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        plan.launch(graph=True)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = ev0.elapsed_time(ev1) / args.steps
-    flops = algo_flops(shapes, T)
+    log(f"[bench] plan ready ({args.compute}), workspace {plan.ws_bytes / 2**30:.1f} GiB")
+    ms, wall_ms = time_plan(plan, args.steps, args.warmup, stream, torch)
     tflops = flops / (ms * 1e-3) / 1e12
-    log(f"[bench] {ms:.3f} ms/step, {tflops:.1f} TFLOP/s (wall {wall / args.steps * 1e3:.3f} ms/step)")
+    log(f"[bench] {ms:.3f} ms/step, {tflops:.1f} TFLOP/s (wall {wall_ms:.3f} ms/step)")
 
     # dominant kernel: the update X = aX + BX of a middle step, timed alone on
     # the stream it is launched on
@@ -264,13 +360,39 @@ def main():
     torch.cuda.synchronize()
 
     extra = {}
-    if not args.no_error and "gaussian" not in meta:
-        errs = []
-        for idx in sorted(set([0, min(4, len(Gs) - 1)])):
-            P = polar_factor(meta, idx, torch).float()
-            errs.append(spec_norm_gpu(plan.outs[idx].float() - P, torch))
-        extra["polar_err_sampled"] = [round(e, 5) for e in errs]
-        log(f"[bench] ||X - UV^T||_2 on sampled matrices: {errs}")
+    if with_err:
+        errs = polar_errors(plan.outs, meta, torch)
+        extra["polar_err"] = err_summary(errs)
+        extra["polar_err_all"] = [round(e, 5) for e in errs]
+        log(f"[bench] ||X - UV^T||_2 over {len(errs)} matrices: {extra['polar_err']}")
+        if "mats" in meta:
+            pred = []
+            for j, (U, sig, V) in enumerate(meta["templates"]):
+                pred.append(round(predicted_polar_error(sig.double().cpu().numpy(), abc), 5))
+            extra["polar_err_predicted_per_shape"] = pred
+        samples[args.compute] = plan.outs[ref_idx].double().cpu().numpy()
+    plan.close()
+    del plan
+    torch.cuda.empty_cache()
+
+    if (args.workload in ("wide-batch", "wide-layer") and args.compute == "bf16"
+            and not args.no_fp8_variant and "gaussian" not in meta):
+        # the e4m3 variant: Gram-side products of steps 1-3 in e4m3, the rest bf16
+        plan8 = pe.Plan(Gs, T=T, abc=abc, compute="fp8", fp8_steps=3, tile=args.tile)
+        ms8, _ = time_plan(plan8, args.steps, args.warmup, stream, torch)
+        v8 = dict(compute="fp8", fp8_steps=3, ms_per_step=round(ms8, 3),
+                  tflops=round(flops / (ms8 * 1e-3) / 1e12, 2), pct_mfma_peak=round(pct_mfma(ms8, 3), 2))
+        log(f"[bench] e4m3 variant {ms8:.3f} ms/step")
+        plan8.launch(graph=True)
+        torch.cuda.synchronize()
+        if with_err:
+            errs8 = polar_errors(plan8.outs, meta, torch)
+            v8["polar_err"] = err_summary(errs8)
+            samples["fp8"] = plan8.outs[ref_idx].double().cpu().numpy()
+        extra["fp8_variant"] = v8
+        plan8.close()
+        del plan8
+        torch.cuda.empty_cache()
 
     if not args.no_plain:
         # plain single-matrix bf16 path: one eager pe_polar per matrix, same schedule
@@ -285,34 +407,27 @@ def main():
         torch.cuda.synchronize()
         plain_ms = e0.elapsed_time(e1)
         extra["plain_single_matrix"] = dict(compute="bf16", ms_per_step=round(plain_ms, 3),
-                                            tflops=round(flops / (plain_ms * 1e-3) / 1e12, 2))
-        if not args.no_error and "gaussian" not in meta:
-            perr = []
-            for idx in sorted(set([0, min(4, len(Gs) - 1)])):
-                P = polar_factor(meta, idx, torch).float()
-                perr.append(round(spec_norm_gpu(outs[idx].float() - P, torch), 5))
-            extra["plain_single_matrix"]["polar_err_sampled"] = perr
+                                            tflops=round(flops / (plain_ms * 1e-3) / 1e12, 2),
+                                            batched_speedup=round(plain_ms / ms, 3))
+        if with_err:
+            extra["plain_single_matrix"]["polar_err"] = err_summary(polar_errors(outs, meta, torch))
         log(f"[bench] plain bf16 path {plain_ms:.3f} ms/step")
         del outs
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
-        idx = len(Gs) - 1
-        G64 = Gs[idx].to(torch.float64).cpu().numpy()
+        G64 = Gs[ref_idx].to(torch.float64).cpu().numpy()
         log(f"[bench] cpu oracle on {G64.shape}")
-        cpu = cpu_baseline(G64, abc, T)
+        cpu, ref = cpu_baseline(G64, abc, T)
         log(f"[bench] cpu oracle {cpu['value']:.4f} TFLOP/s")
+        if samples:
+            extra["relF_vs_fp64_oracle"] = {k: float(f"{rel_fro_np(v, ref):.4e}") for k, v in samples.items()}
+            extra["relF_vs_fp64_oracle"]["matrix"] = f"#{ref_idx} {G64.shape[0]}x{G64.shape[1]}"
+            log(f"[bench] relF vs FP64 oracle: {extra['relF_vs_fp64_oracle']}")
 
     peak = PEAK_BF16_TFLOPS
     traffic = measured_traffic(args.workload, args.compute, args.tile, args.fp8_steps)
-    # MFMA-peak fraction with each product at its own precision's dense peak
-    fp8_fl = 0.0
-    if args.compute == "fp8":
-        for m, n in shapes:
-            s_, L_ = min(m, n), max(m, n)
-            fp8_fl += (float(s_) * s_ * L_ + float(s_) ** 3) * min(args.fp8_steps, T)
-    pct_mfma = 100.0 * ((flops - fp8_fl) / (PEAK_BF16_TFLOPS * 1e12) +
-                        fp8_fl / (PEAK_FP8_TFLOPS * 1e12)) / (ms * 1e-3)
     out = {
         "metric": "polar TFLOP/s & % MFMA peak at fixed ||X-UV^T||_2, batched vs plain bf16",
         "value": round(tflops, 3),
@@ -330,7 +445,7 @@ def main():
                    "compute": args.compute, "fp8_steps": args.fp8_steps, "tile": args.tile,
                    "shapes": sorted(set(shapes))},
         "pct_bf16_peak": round(100.0 * tflops / peak, 2),
-        "pct_mfma_peak": round(pct_mfma, 2),
+        "pct_mfma_peak": round(pct_mfma(ms, args.fp8_steps if args.compute == "fp8" else 0), 2),
         "matrices_per_s": round(len(Gs) / (ms * 1e-3), 2),
         "dense_equivalent_tflops": round(dense_flops(shapes, T) / (ms * 1e-3) / 1e12, 2),
         "roofline": {"bound": "mfma", "achieved": round(upd_tf, 2), "peak": peak,
@@ -344,7 +459,6 @@ def main():
     }
     out.update(extra)
     print(json.dumps(out), flush=True)
-    plan.close()
 
 
 if __name__ == "__main__":

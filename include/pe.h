@@ -62,17 +62,21 @@ typedef enum { PE_COMPUTE_F32 = 0, PE_COMPUTE_BF16 = 1, PE_COMPUTE_FP8 = 2 } pe_
  *
  * Theorem 1 (greedy is optimal) with the degree-5 Remez exchange of
  * Appendix E (Algorithm 3, eq. linearsystem) and the finite-precision changes
- * of Section 3.4 / Appendix F, as the offline generator of Appendix A.2 does:
+ * of Section 3.4 / Appendix F:
  *   u_1 = 1, l_1 = ell;  for t = 1..T:
  *     p_t = minimax odd quintic for 1 on [max(l_t, cushion*u_t), u_t]
- *           (Newton-Schulz (15/8, -10/8, 3/8) once max(l_t,...)/u_t >= 1-5e-6);
- *     p_t <- p_t * 2 / (p_t(l_t) + p_t(u_t))          (re-centring)
+ *           (Newton-Schulz (15/8, -10/8, 3/8) once the interval's ratio is
+ *           within eps^(1/3) of 1, Algorithm 3's degenerate branch);
+ *     p_t <- p_t * 2 / (p_t(l_t) + p_t(u_t))   (p(l_t), p(u_t) symmetric about 1)
  *     l_{t+1} = p_t(l_t),  u_{t+1} = 2 - l_{t+1}      (eq. newbounds)
  *   then every non-Newton-Schulz step is replaced by p_t(x / safety).
+ * The default cushion applies Appendix F's ratio-1/10 rule to the image: the
+ * r for which the minimax quintic on [r, 1] maps it onto an interval of ratio
+ * 1/10 (levelled error 9/11), found by bisection (0.0240732742418276...).
  * cushion < 0 selects Algorithm 1's rule [max(l_t, u_t/10), u_t] (no re-centring).
  * ------------------------------------------------------------------------- */
 typedef struct {
-  double cushion;          /* default 0.02407327424182761; 0 = pure greedy */
+  double cushion;          /* default: the ratio-1/10 root above; 0 = pure greedy */
   double safety;           /* default 1.01; 1.0 = off */
   int32_t safety_on_last;  /* default 1; 0 = leave the last step unscaled */
 } pe_coeff_opts;
@@ -121,6 +125,13 @@ typedef struct {
   const float* predictor;  /* device, PE_MLP_PARAMS floats, or NULL */
   int32_t force_class;     /* -1: the network's choice; 0..7: this class (tests) */
   float fallback_tau;      /* <= 0: no estimate and no fallback */
+  /* Split-K of the two Gram-side products (A = X X^T, A^2).  A launch with
+   * fewer upper-triangle tiles than the device has room for splits each
+   * tile's k range into up to this many partial tiles, summed in split order
+   * by a reduction kernel (deterministic).  0 = library choice (up to 64),
+   * 1 = never split, n in 2..64 = at most n.  Results agree across settings up
+   * to the FP32 summation order.  PE_EINVAL outside 0..64. */
+  int32_t split_k;
 } pe_opts;
 
 #define PE_CLASSES 8
@@ -207,10 +218,13 @@ pe_status pe_mlp_train_step(float* params, float* m, float* v, int32_t step, flo
  * paper_2505_16932_amd/autotune.py); loading a table replaces the previous one. */
 int32_t pe_tile_count(void);
 const char* pe_tile_name(int32_t tile_id);
-/* Lines "<shape-class> <tile-id>" ('#' starts a comment); tile-id 1 or 2.
- * With a table loaded and opts.tile = 0, each matrix of a call votes for its
- * class's tile with its flop count (3 s^2 L + s^3); calls with a matrix whose
- * class is missing keep the built-in choice.  PE_EINVAL on a malformed file. */
+/* Lines "<shape-class>_<regime> <tile-id>" ('#' starts a comment); tile-id 1
+ * or 2; regime x1 (a call with one matrix) or xN (a batch).  With a table
+ * loaded and opts.tile = 0, each matrix of a call takes its class's tile, and
+ * every phase of the call launches once per (precision, tile) class present;
+ * matrices whose class is missing take the built-in rule (256 for s >= 512 in
+ * calls with at least 256 update tiles of 256, else 128).  FP32 matrices use
+ * the 128 tile unless opts.tile forces 256.  PE_EINVAL on a malformed file. */
 pe_status pe_tile_table_load(const char* path);
 /* Shape class of an m x n matrix for the compute mode (the table's key). */
 const char* pe_shape_class(int32_t compute, int64_t m, int64_t n);

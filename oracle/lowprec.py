@@ -64,30 +64,3 @@ def e4m3_code(x) -> np.ndarray:
     m = np.round((a / np.ldexp(1.0, e.astype(np.int64)) - 1.0) * 8.0)
     code[nrm] = (((e[nrm] + 7).astype(np.uint16) << 3) | m[nrm].astype(np.uint16))
     return (code | sign).astype(np.uint8)
-
-
-def iteration_bf16_operands(G, abc):
-    """Model of the bf16 path's rounding points, in float64 otherwise.
-
-    The scale sigma = 1/(1.01 ||G||_F + 1e-7) multiplies step 1's products
-    after rounding, so step 1 takes the operand bf16(G) and
-        A_1 = sigma^2 bf16(G) bf16(G)^T,  X_1 = sigma (a G + bf16(B_1) bf16(G));
-    later steps take bf16(X) for the Gram product and the update, bf16(A) for
-    A^2 and for the b A term of B, and bf16(B) for the update, while the a X
-    term uses the unrounded iterate (the FP32 master).  The distance of this model from the FP64
-    iteration is the part of the error that bf16 operands cause at all; it sets
-    a per-input tolerance where the 3e-2 bar is out of reach of the arithmetic."""
-    G = np.asarray(G, dtype=np.float64)
-    m, n = G.shape
-    tall = m > n
-    Gt = G.T if tall else G
-    sigma = 1.0 / (1.01 * np.sqrt(np.sum(G * G)) + 1e-7)
-    X = Gt.copy()
-    for t, (a, b, c) in enumerate(np.asarray(abc, dtype=np.float64).reshape(-1, 3)):
-        scale = sigma if t == 0 else 1.0
-        Xo = round_bf16(X.astype(np.float32))
-        A = scale * scale * (Xo @ Xo.T)
-        Ao = round_bf16(A.astype(np.float32))
-        B = b * Ao + c * (Ao @ Ao)
-        X = scale * (a * X + round_bf16(B.astype(np.float32)) @ Xo)
-    return X.T if tall else X

@@ -13,13 +13,18 @@ Follows:
   scaled to u (the degenerate branch of Algorithm 3).
 * Appendix E, eq. (deg3_solution): closed form for degree 3.
 * Section 3.4 / Appendix F: safety factor p(x/1.01) and cushioning of the
-  lower end of the design interval; the coefficient listing of Appendix A.1
-  uses the cushion 0.02407327424182761 * u with a rescaling that re-centres
-  p(l_t) and p(u_t) about 1.
+  lower end of the design interval.  Appendix F states the cushion as a ratio
+  rule ("select the update as though l_t = u_t/10") and says its code uses a
+  different factor; the printed coefficient table is reproduced by the ratio
+  rule applied to the image: the design interval [r u_t, u_t] is widened until
+  its minimax quintic maps it onto an interval of ratio 1/10, i.e. r is the
+  root of E(r) = 9/11 (``ratio_cushion``), followed by a rescaling that
+  re-centres p(l_t) and p(u_t) about 1.
 
 Readings where the paper is inconsistent (recorded in the design doc):
-* the degenerate branch uses the threshold 1 - 5e-6 (Appendix A.2) rather than
-  1 - eps^{1/3} (Algorithm 3);
+* the degenerate branch uses Algorithm 3's threshold l/u >= 1 - eps^(1/3)
+  (eps = 1.11e-16); the exchange stops when |E| changes by at most 16 eps
+  (the rounding level of the 4x4 solve);
 * when a step is degenerate we emit the exact Newton-Schulz quintic
   (15/8, -10/8, 3/8), which is what the printed coefficient table holds;
 * l_{t+1} is computed from the polynomial *before* the safety factor is
@@ -34,12 +39,9 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-# Cushion factor of the printed coefficient generator (Appendix A.2).  It is
-# the r for which the minimax quintic on [r, 1] has error E = 9/11, i.e. maps
-# [r, 1] onto an interval of ratio 1/10 (pinned in tests).
-CUSHION = 0.02407327424182761
+EPS_DOUBLE = 1.11e-16                      # Algorithm 3's machine epsilon
 SAFETY = 1.01
-DEGENERATE_RATIO = 1.0 - 5e-6
+DEGENERATE_RATIO = 1.0 - EPS_DOUBLE ** (1.0 / 3.0)
 NS5 = (15.0 / 8.0, -10.0 / 8.0, 3.0 / 8.0)
 
 
@@ -62,7 +64,26 @@ class RemezResult:
     degenerate: bool = False
 
 
-def remez_quintic(lo: float, hi: float, tol: float = 1e-15, max_iter: int = 100) -> RemezResult:
+def _solve_refined(M, r):
+    """Solve the 4x4 system of eq. (linearsystem) with one step of iterative
+    refinement, the residual taken in extended precision: as l/u -> 1 the
+    system's condition number grows (Appendix E notes it; ~2e6 on the seventh
+    step of the l = 1e-3 schedule), and a plain float64 solve then loses six
+    digits of the coefficients."""
+    z = np.linalg.solve(M, r)
+    res = (np.asarray(r, dtype=np.longdouble)
+           - np.asarray(M, dtype=np.longdouble) @ np.asarray(z, dtype=np.longdouble))
+    return z + np.linalg.solve(M, res.astype(np.float64))
+
+
+# Algorithm 3 repeats the exchange until |E| stops changing; in float64 the
+# change bottoms out at the rounding level of the 4x4 solve (a few ulps of E,
+# and a cycle between two values two ulps apart never meets an eps test), so
+# the exchange stops once |E| moves by at most 16 eps.
+REMEZ_TOL = 16 * EPS_DOUBLE
+
+
+def remez_quintic(lo: float, hi: float, tol: float = REMEZ_TOL, max_iter: int = 100) -> RemezResult:
     """Minimax odd quintic approximation of 1 on [lo, hi] (Appendix E, Alg. 3).
 
     Returns the coefficients, the levelled error E of the last exchange and the
@@ -84,7 +105,7 @@ def remez_quintic(lo: float, hi: float, tol: float = 1e-15, max_iter: int = 100)
         pts = np.array([lo, x1, x2, hi])
         # columns: x, x^3, x^5, alternating sign for the levelled error
         M = np.stack([pts, pts ** 3, pts ** 5, np.array([1.0, -1.0, 1.0, -1.0])], axis=1)
-        a, b, c, E = np.linalg.solve(M, np.ones(4))
+        a, b, c, E = _solve_refined(M, np.ones(4))
         # critical points of p: 5c y^2 + 3b y + a = 0, y = x^2
         disc = math.sqrt(9.0 * b * b - 20.0 * a * c)
         y_small = (-3.0 * b - disc) / (10.0 * c)
@@ -94,6 +115,31 @@ def remez_quintic(lo: float, hi: float, tol: float = 1e-15, max_iter: int = 100)
             break
         prev = E
     return RemezResult(float(a), float(b), float(c), float(E), it, (lo, x1, x2, hi), False)
+
+
+def ratio_cushion(ratio: float = 0.1) -> float:
+    """The cushion r of Appendix F's ratio rule applied to the image: the
+    minimax quintic for 1 on [r, 1] has levelled error E with
+    (1 - E) / (1 + E) = ratio, i.e. E = (1 - ratio) / (1 + ratio) (9/11 for
+    the ratio 1/10).  E(r) decreases as r grows (the interval shrinks), so the
+    root is bracketed and found by bisection to the spacing of doubles; the
+    minimax error on [r u, u] does not depend on u."""
+    target = (1.0 - ratio) / (1.0 + ratio)
+    a, b = 1e-6, 0.5
+    assert abs(remez_quintic(a, 1.0).E) > target > abs(remez_quintic(b, 1.0).E)
+    while True:
+        mid = 0.5 * (a + b)
+        if mid <= a or mid >= b:
+            break
+        if abs(remez_quintic(mid, 1.0).E) > target:
+            a = mid
+        else:
+            b = mid
+    return 0.5 * (a + b)
+
+
+# cushion factor of the default schedule (Appendix F's ratio rule, see above)
+CUSHION = ratio_cushion(0.1)
 
 
 def cubic_closed_form(lo: float, hi: float):

@@ -58,7 +58,7 @@ class Opts(ctypes.Structure):
                 ("compute", ctypes.c_int32), ("fp8_steps", ctypes.c_int32),
                 ("norm_mode", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("predictor", ctypes.c_void_p), ("force_class", ctypes.c_int32),
-                ("fallback_tau", ctypes.c_float)]
+                ("fallback_tau", ctypes.c_float), ("split_k", ctypes.c_int32)]
 
 
 MLP_PARAMS = 5768
@@ -146,7 +146,7 @@ def lib() -> ctypes.CDLL:
 
 def _check(st: int, where: str):
     if st != 0:
-        detail = lib().pe_last_error().decode() if st == 5 else ""
+        detail = lib().pe_last_error().decode() if st in (4, 5) else ""
         raise PEError(st, where, detail)
 
 
@@ -205,7 +205,7 @@ def _matrix(G, X) -> Matrix:
 
 
 def _opts(T, abc, compute, fp8_steps, norm_mode, tile, predictor=None, force_class=-1,
-          fallback_tau=0.0):
+          fallback_tau=0.0, split_k=0):
     abc = np.ascontiguousarray(np.asarray(abc, dtype=np.float64).reshape(-1))
     if abc.size != 3 * T:
         raise ValueError("abc must hold 3*T coefficients")
@@ -215,7 +215,8 @@ def _opts(T, abc, compute, fp8_steps, norm_mode, tile, predictor=None, force_cla
             raise ValueError("predictor must be a float32 device tensor of MLP_PARAMS values")
         pred = predictor.data_ptr()
     o = Opts(int(T), abc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), COMPUTE[compute],
-             int(fp8_steps), int(norm_mode), int(tile), pred, int(force_class), float(fallback_tau))
+             int(fp8_steps), int(norm_mode), int(tile), pred, int(force_class), float(fallback_tau),
+             int(split_k))
     return o, abc
 
 
@@ -312,17 +313,17 @@ class MLPTrainer:
 
 def polar(G, T: int = 5, ell: float = 1e-3, abc=None, compute: str = "bf16", out=None,
           out_dtype=None, fp8_steps: int = 0, norm_mode: int = 0, tile: int = 0, stream=None,
-          predictor=None, force_class: int = -1, fallback_tau: float = 0.0):
+          predictor=None, force_class: int = -1, fallback_tau: float = 0.0, split_k: int = 0):
     """X_T for one matrix (pe_polar).  Returns a new tensor unless ``out`` is given."""
     return polar_batched([G], T, ell, abc, compute, [out] if out is not None else None,
                          out_dtype, fp8_steps, norm_mode, tile, stream, predictor, force_class,
-                         fallback_tau, _single=True)[0]
+                         fallback_tau, split_k=split_k, _single=True)[0]
 
 
 def polar_batched(Gs, T: int = 5, ell: float = 1e-3, abc=None, compute: str = "bf16", outs=None,
                   out_dtype=None, fp8_steps: int = 0, norm_mode: int = 0, tile: int = 0,
                   stream=None, predictor=None, force_class: int = -1, fallback_tau: float = 0.0,
-                  _single: bool = False):
+                  split_k: int = 0, _single: bool = False):
     """X_T for a list of matrices of any shapes (pe_polar_batched)."""
     import torch
     Gs = list(Gs)
@@ -330,7 +331,7 @@ def polar_batched(Gs, T: int = 5, ell: float = 1e-3, abc=None, compute: str = "b
         outs = [torch.empty(G.shape, dtype=out_dtype or G.dtype, device=G.device) for G in Gs]
     sched = _schedule(T, ell, abc)
     o, _keep = _opts(T, sched, compute, fp8_steps, norm_mode, tile, predictor, force_class,
-                     fallback_tau)
+                     fallback_tau, split_k)
     mats = (Matrix * max(1, len(Gs)))()
     for i, (G, X) in enumerate(zip(Gs, outs)):
         mats[i] = _matrix(G, X)
@@ -371,7 +372,7 @@ class Plan:
     def __init__(self, Gs, outs=None, T: int = 5, ell: float = 1e-3, abc=None, compute: str = "bf16",
                  out_dtype=None, fp8_steps: int = 0, norm_mode: int = 0, tile: int = 0, stream=None,
                  predictor=None, force_class: int = -1, fallback_tau: float = 0.0,
-                 ws_fill=None):
+                 ws_fill=None, split_k: int = 0):
         import torch
         self.Gs = list(Gs)
         self.outs = outs if outs is not None else [
@@ -380,7 +381,7 @@ class Plan:
         self.abc = _schedule(T, ell, abc)
         self._predictor = predictor
         o, self._abc_keep = _opts(T, self.abc, compute, fp8_steps, norm_mode, tile, predictor,
-                                  force_class, fallback_tau)
+                                  force_class, fallback_tau, split_k)
         self._mats = (Matrix * max(1, len(self.Gs)))()
         for i, (G, X) in enumerate(zip(self.Gs, self.outs)):
             self._mats[i] = _matrix(G, X)

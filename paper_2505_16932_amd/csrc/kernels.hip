@@ -1058,10 +1058,11 @@ __device__ __forceinline__ void load_frag_row(const S* __restrict__ src, size_t 
     }
 }
 
-// red: LDS scratch of at least 4 * NW doubles for the moment reduction (the
-// GEMM kernel lends its operand ring, free once the main loop is done; a
-// kernel with a single LDS object keeps the compiler's LDS-DMA wait tracking
-// from turning into a full vmcnt(0) wait after every stage's loads).
+// red: LDS scratch of at least 4 * NW doubles for the epilogue's block
+// reductions (the GEMM kernel gives a tail of its one LDS array, past the
+// operand ring and the staging area: a kernel with a single LDS object keeps
+// the compiler's LDS-DMA wait tracking from turning into a full vmcnt(0) wait
+// after every stage's loads).
 // A is exactly symmetric as stored (a tile's mirror holds the same bf16
 // values, and a diagonal tile sums the same products in the same order at (i,j)
 // and (j,i)), so the four consecutive rows i..i+3 of a lane at column j are the
@@ -1116,7 +1117,12 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
     alpha *= sg * sg;
   }
   const float calpha = c * deq;
+  // B - beta I: the shift leaves the diagonal of the real s x s block
+  const bool shifted = kind == KIND_A2 && !args.raw_a2;
+  const float beta = shifted ? shift_beta(d, b, c) : 0.0f;
+  if (shifted && ti == 0 && tj == 0 && threadIdx.x == 0) d.scal[kScBeta] = beta;
   float amax = 0.0f;
+  float trs = 0.0f, frs = 0.0f;  // Gram: this lane's share of tr(A) and of ||A||_F^2 over the tile
   double mom[4] = {0.0, 0.0, 0.0, 0.0};
   // the A^2 kinds read A: FP32 on the fp32 path, its bf16 copy otherwise
   const bool reads_a = kind == KIND_A2;
@@ -1151,6 +1157,8 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
             if (P == kF32) d.Af[o] = v[r];
             else if constexpr (!STAGE) ((uint16_t*)d.As)[o] = f2bf(v[r]);
             amax = fmaxf(amax, fabsf(v[r]));
+            // (staged tiles take their sum of squares from LDS during the copy-out)
+            if constexpr (!STAGE) frs = __builtin_fmaf(v[r], v[r], frs);
           } else if (args.raw_a2) {
             // learned path, step 1: keep A^2 and accumulate tr(A^k) partials;
             // the combine kernel forms B once the schedule class is known
@@ -1166,6 +1174,7 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
           } else {
             // same operation order as the learned path's combine kernel
             v[r] = __builtin_fmaf(calpha, x, b * cur.x[fn][g][r]);
+            if (ti == tj && i + r == j && j < d.s) v[r] -= beta;
             if (P == kF32) ((float*)d.Bs)[o] = v[r];
             else if constexpr (!STAGE) ((uint16_t*)d.Bs)[o] = f2bf(v[r]);
           }
@@ -1215,11 +1224,55 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
                                               (__attribute__((address_space(3))) i16x4*)(p)));
       }
       *(u32x4*)(own + (size_t)(16 * ib + s) * sp) = (u32x4){h[0][0], h[0][1], h[1][0], h[1][1]};
+      if (kind == KIND_GRAM) {
+#pragma unroll
+        for (int rd = 0; rd < 2; ++rd)
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const float lo = __uint_as_float(h[rd][e] << 16), hi = __uint_as_float(h[rd][e] & 0xffff0000u);
+            frs = __builtin_fmaf(lo, lo, frs);
+            frs = __builtin_fmaf(hi, hi, frs);
+          }
+      }
     }
     // (the next tile's prologue starts with a barrier before it refills the ring)
   }
   // the A^2 product of the same step quantises A with this maximum
   if (kind == KIND_GRAM && args.fp8) wave_amax_atomic(amax, d.scal + kScAmaxA + args.t);
+  if (kind == KIND_GRAM) {
+    // the tile's partials of tr(A) and ||A||_F^2 (an off-diagonal tile also
+    // stands for its mirror), summed in a fixed order; the diagonal is read
+    // back once the tile is stored (from the staging area, else from memory:
+    // the block's own stores are visible to it after the barrier)
+    float* rf = (float*)red;
+    __syncthreads();  // tile stored; the previous tile's reader of rf is done
+    if (ti == tj && threadIdx.x < BT) {
+      const int q = threadIdx.x;
+      if constexpr (STAGE) trs = bf2f(*(const uint16_t*)(smem + q * kXtStageRow + q * 2));
+      else if constexpr (P == kF32) trs = d.Af[(size_t)(ti * BT + q) * sp + tj * BT + q];
+      else trs = bf2f(((const uint16_t*)d.As)[(size_t)(ti * BT + q) * sp + tj * BT + q]);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      trs += __shfl_xor(trs, off);
+      frs += __shfl_xor(frs, off);
+    }
+    if (lane == 0) {
+      rf[2 * wave] = trs;
+      rf[2 * wave + 1] = frs;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float t0 = 0.0f, t1 = 0.0f;
+#pragma unroll
+      for (int w = 0; w < W::NW; ++w) {
+        t0 += rf[2 * w];
+        t1 += rf[2 * w + 1];
+      }
+      const int tileid = tri_index(ti, tj, d.nb);
+      d.trp[2 * tileid] = t0;
+      d.trp[2 * tileid + 1] = (ti == tj ? 1.0f : 2.0f) * t1;
+    }
+  }
   if (kind == KIND_A2 && args.raw_a2) {
     // fixed-order block reduction of the tile's moment partials
     const int tileid = tri_index(ti, tj, d.nb);
@@ -1263,6 +1316,7 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
   const int wm = wave / W::WGN, wn = wave % W::WGN;
   float a, b, c;
   step_coef(args, d, &a, &b, &c);
+  a += d.scal[kScBeta];  // the B operand holds B - beta I
   const float alpha = (args.t == 0) ? d.scal[kScScale] : 1.0f;
   const size_t Lp = d.Lp, sp = d.sp;
   void* XTn = (args.t & 1) ? d.XT0 : d.XT1;
@@ -1359,7 +1413,10 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
   constexpr bool kStageMirror = P != kF32 && BT == 256;
   constexpr int LDSB = (BT == 256 && P != kF32 && KIND != KIND_UPD && LDSB0 < kXtStageBytes)
                            ? kXtStageBytes : LDSB0;
-  __shared__ __attribute__((aligned(16))) char smem[LDSB];
+  // SYRK kinds: a small tail past the ring for the epilogue's block reductions
+  constexpr int kRedTail = (KIND == KIND_GRAM || KIND == KIND_A2) ? 256 : 0;
+  static_assert(kRedTail == 0 || kRedTail >= 4 * W::NW * 8, "moment reduction fits the tail");
+  __shared__ __attribute__((aligned(16))) char smem[LDSB + kRedTail];
   for (int slot = blockIdx.x; slot < args.total; slot += gridDim.x) {
     const int item = xcd_item(slot, args.total);
     const int pos = find_mat(args.offs, args.count, item);
@@ -1419,7 +1476,7 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
         if (k1 > k0) gemm_nt_tile<T, BT>(Op, Op, K, ti * BT, tj * BT, k0, k1, smem, acc);
       }
       if (split == 1) {
-        epi_syrk<P, BT, kStageMirror>(args, d, KIND, ti, tj, deq, acc, (double*)smem, smem);
+        epi_syrk<P, BT, kStageMirror>(args, d, KIND, ti, tj, deq, acc, (double*)(smem + LDSB), smem);
       } else {
         // partial tile: float4 q of thread t at ((tile*split + ksp)*Q + q)*NT + t
         constexpr int Q = 4 * W::FN * C::ACC / 4;

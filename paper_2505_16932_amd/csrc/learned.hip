@@ -247,7 +247,9 @@ __global__ __launch_bounds__(64) void select_kernel(KArgs args) {
   }
 }
 
-// B = b_c A + c_c A^2 over the padded s x s block, once the class is known.
+// B - beta I, B = b_c A + c_c A^2, over the padded s x s block once the class
+// is known (beta = tr(B)/s from the step-1 Gram partials, as in the fused A^2
+// epilogue; the diagonal is shifted on the real s rows only).
 template <int P>
 __global__ __launch_bounds__(256) void combine_kernel(KArgs args) {
   for (int item = blockIdx.x; item < args.total; item += gridDim.x) {
@@ -262,12 +264,15 @@ __global__ __launch_bounds__(256) void combine_kernel(KArgs args) {
     if (cls < 0 || cls >= kClasses) cls = args.fixed_class;
     const float* cf = args.sel_coef + ((size_t)cls * args.tmax + args.t) * 3;
     const float b = cf[1], c = cf[2];
+    const float beta = shift_beta(d, b, c);
+    if (row == 0 && threadIdx.x == 0) d.scal[kScBeta] = beta;
     const size_t base = (size_t)row * d.sp;
     for (int j = threadIdx.x; j < d.sp; j += blockDim.x) {
       const float av = P == kF32 ? d.Af[base + j]
                                  : __uint_as_float((uint32_t)((const uint16_t*)d.As)[base + j] << 16);
       // same operation order as the fused A^2 epilogue (there c * deq, deq = 1)
-      const float v = __builtin_fmaf(c, d.A2f[base + j], b * av);
+      float v = __builtin_fmaf(c, d.A2f[base + j], b * av);
+      if (j == row && row < d.s) v -= beta;
       if (P == kF32) ((float*)d.Bs)[base + j] = v;
       else {
         uint32_t u = __float_as_uint(v);

@@ -14,12 +14,14 @@
 //   Af      sp x sp  fp32   A = X X^T (fp32 path only)
 //   As      sp x sp  bf16   A in bf16 on the bf16/fp8 paths, read by A^2 and by
 //                           the bA term of B (fp32 path: Af itself)
-//   Bs      sp x sp  bf16 or fp32   B = bA + cA^2
+//   Bs      sp x sp  bf16 or fp32   B - beta I, B = bA + cA^2 (beta: see shift_beta)
 //   Xq, Aq  sp x Lp, sp x sp  e4m3  operand copies for the FP8 steps (256 tile)
 //   part    split-K partial tiles of the Gram-side products
 //   red     per-tile partial sums of squares (fp64) and maxima (fp32) of G
+//   trp     per-tile partials of tr(A_t) and ||A_t||_F^2 (fp32), for the shift beta_t
 //   scal    per-matrix scalars (scale, amax values), cnt: arrival counters
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace pe {
@@ -38,6 +40,7 @@ enum : int32_t {
   kScScale = 0,    // sigma = 1 / (1.01 ||G||_F + 1e-7)
   kScAmaxG = 1,    // max |G| (float bits)
   kScFro = 2,      // ||G||_F as float
+  kScBeta = 3,     // shift beta_t = tr(B_t)/s of the current step (update: a + beta)
   kScAmaxX = 8,    // +t : max |X_t| (uint bits of a non-negative float), t = 0..63
   kScAmaxA = 72,   // +t : max |A_t| for step t (0-based)
   kScN = 136
@@ -61,6 +64,7 @@ struct MatDesc {
   double* red;      // [n_prep] doubles then [n_prep] floats
   float* scal;      // [kScN]
   uint32_t* cnt;    // [4]
+  float* trp;       // [syrk_nt][2] per-tile partials of tr(A) and ||A||_F^2 (Gram epilogue)
   int32_t n_prep, syrk_nt, upd_nt, gram_split;
   int32_t a2_split, bt, g_vec, o_vec;  // bt: block tile edge; g_vec / o_vec: 16-byte
                                        // loads of G / stores of the bf16 output
@@ -99,6 +103,31 @@ struct KArgs {
   int32_t est_phase;     // power-iteration phase selector
   const int32_t* ord;    // position -> matrix of this phase's item order (nullptr: identity)
 };
+
+// Spectral shift of the update.  In real arithmetic
+//   X_{t+1} = a X + B X = (a + beta) X + (B - beta I) X
+// for any beta.  The product takes bf16 copies of its operands, whose rounding
+// errors enter as (B - beta I) dX and dB X; beta = tr(B) / s, the mean
+// eigenvalue of B, minimises ||B - beta I||_F and with it the error carried
+// by isotropic rounding noise (on inputs whose singular values sit close
+// together, B is close to a multiple of I and the unshifted product rounds away
+// most of the update).  tr(B) = b tr(A) + c ||A||_F^2 for symmetric A; the Gram
+// epilogue leaves per-tile partials of both, and every caller reduces them in
+// the same fixed order, so all blocks agree on beta bit for bit.
+__device__ __forceinline__ float shift_beta(const MatDesc& d, float b, float c) {
+  const int lane = threadIdx.x & 63;
+  float tr = 0.0f, fr = 0.0f;
+  for (int u = lane; u < d.syrk_nt; u += 64) {
+    tr += d.trp[2 * u];
+    fr += d.trp[2 * u + 1];
+  }
+  // butterfly sums: every lane ends with the same bits (addition commutes exactly)
+  for (int off = 32; off > 0; off >>= 1) {
+    tr += __shfl_xor(tr, off);
+    fr += __shfl_xor(fr, off);
+  }
+  return d.s > 0 ? (b * tr + c * fr) / (float)d.s : 0.0f;
+}
 
 constexpr int kClasses = 8;
 constexpr int kFeat = 16;

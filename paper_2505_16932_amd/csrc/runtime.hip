@@ -73,17 +73,31 @@ pe_status hip_fail(hipError_t e, const char* where) {
   return PE_EHIP;
 }
 
+// Launch classes: (precision, block tile).  Every phase launches once per class
+// present in a call, over the items of that class's matrices only, so one
+// grouped call can mix tiles (per-shape-class choices of the autotuned table)
+// and precisions (matrices too small for bf16 rounding to average out run
+// FP32 operands inside a bf16 call).
+constexpr int kNCls = 4;
+inline int cls_of(int prec, int bt) { return (prec == kF32 ? 0 : 2) + (bt == kTileLarge ? 1 : 0); }
+inline int cls_prec(int c) { return c < 2 ? kF32 : kBF16; }
+inline int cls_bt(int c) { return (c & 1) ? kTileLarge : kTileSmall; }
+
 struct Layout {
   std::vector<MatDesc> descs;           // device pointers filled when ws != nullptr
-  std::vector<int32_t> offs[PH_N];      // count + 1 each
-  int32_t totals[PH_N] = {0};
+  std::vector<int32_t> prec, bt;        // per matrix
+  // item tables: offs[ph][cls] holds count + 1 prefix offsets in which the
+  // matrices of other classes contribute no items (phases that do not depend
+  // on the class -- the estimate's matrix-vector products -- keep every
+  // matrix in class 0's table)
+  std::vector<int32_t> offs[PH_N][kNCls];
+  int32_t totals[PH_N][kNCls] = {};
+  // Gram items per class ordered by matrix, longest k (Lp) first: per-tile
+  // work is proportional to Lp, and persistent blocks take items round-robin,
+  // so long tiles first and short ones last balance the CUs
+  std::vector<int32_t> ord_gram[kNCls];
   size_t bytes = 0;
   size_t descs_off = 0, offs_off = 0, coef_off = 0;
-  // Gram items ordered by matrix, longest k (Lp) first: per-tile work is
-  // proportional to Lp, and persistent blocks take items round-robin, so
-  // long tiles first and short ones last balance the CUs
-  std::vector<int32_t> ord_gram;
-  int bt = kTileSmall;
 };
 
 bool valid_matrix(const pe_matrix& m) {
@@ -109,10 +123,9 @@ pe_status check_opts(const pe_opts* o) {
     if (!std::isfinite(o->abc[i])) return PE_EINVAL;
   if (o->force_class < -1 || o->force_class >= kClasses) return PE_EINVAL;
   if (!std::isfinite(o->fallback_tau)) return PE_EINVAL;
+  if (o->split_k < 0 || o->split_k > 64) return PE_EINVAL;
   return PE_OK;
 }
-
-int prec_of(const pe_opts* o) { return o->compute == PE_COMPUTE_F32 ? kF32 : kBF16; }
 
 // Block tile for a call: 256 x 256 (32x32 MFMA fragments, wave tile 128 x 128)
 // halves the LDS and L2 traffic per flop of the 128 x 128 tile, but pads s and
@@ -136,59 +149,66 @@ std::string shape_class(int prec, int64_t s, int64_t L) {
   return buf;
 }
 
-int choose_tile(int count, const pe_matrix* mats, const pe_opts* o) {
+// Precision of one matrix: FP32 on the FP32 path; on the bf16/FP8 paths FP32
+// as well when the smaller side is below kTinyS, where a handful of singular
+// values leave bf16 rounding errors nothing to average over (relative errors
+// up to ~1e-1 at s = 2-8 on Gaussian inputs) and the products cost nothing.
+constexpr int64_t kTinyS = 16;
+int prec_for(const pe_opts* o, int64_t s) {
+  if (o->compute == PE_COMPUTE_F32 || s < kTinyS) return kF32;
+  return kBF16;
+}
+
+// Block tile of one matrix.  Forced by opts.tile; else the autotuned table's
+// entry for the matrix's shape class in the call's regime ("x1": a call with
+// one matrix, "xN": a batch); else 256 for bf16 matrices with s >= 512 in
+// calls whose update has at least one 256-tile per CU, 128 otherwise.
+int tile_for(const pe_opts* o, int prec, int64_t s, int64_t L, int count, int64_t upd_tiles256) {
   if (o->tile == 1) return kTileSmall;
   if (o->tile == 2) return kTileLarge;
+  if (prec == kF32) return kTileSmall;
   {
-    // autotuned: every matrix votes for its class's tile with its flop count
     std::lock_guard<std::mutex> lk(g_tab_mu);
     if (!g_tile_table.empty()) {
-      double w[3] = {0, 0, 0};
-      bool all_known = true;
-      for (int i = 0; i < count; ++i) {
-        const pe_matrix& m = mats[i];
-        if (m.m <= 0 || m.n <= 0) continue;
-        const int64_t s = std::min(m.m, m.n), L = std::max(m.m, m.n);
-        auto it = g_tile_table.find(shape_class(prec_of(o), s, L));
-        if (it == g_tile_table.end()) { all_known = false; break; }
-        w[it->second] += 3.0 * (double)s * s * L + (double)s * s * s;
-      }
-      if (all_known && (w[1] > 0 || w[2] > 0)) return w[2] > w[1] ? kTileLarge : kTileSmall;
+      auto it = g_tile_table.find(shape_class(prec, s, L) + (count == 1 ? "_x1" : "_xN"));
+      if (it != g_tile_table.end()) return it->second == 2 ? kTileLarge : kTileSmall;
     }
   }
-  if (prec_of(o) == kF32) return kTileSmall;
-  int64_t upd_tiles = 0;
-  bool any = false;
-  for (int i = 0; i < count; ++i) {
-    const pe_matrix& m = mats[i];
-    if (m.m <= 0 || m.n <= 0) continue;
-    any = true;
-    const int64_t s = std::min(m.m, m.n), L = std::max(m.m, m.n);
-    if (s < 512) return kTileSmall;
-    upd_tiles += round_up(s, kTileLarge) / kTileLarge * (round_up(L, kTileLarge) / kTileLarge);
-  }
-  return (any && upd_tiles >= 256) ? kTileLarge : kTileSmall;
+  return (s >= 512 && upd_tiles256 >= 256) ? kTileLarge : kTileSmall;
 }
 
 // Build the per-matrix descriptors and the item tables.  With ws == nullptr
 // only sizes are computed.
 pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char* ws, Layout* L) {
-  const int prec = prec_of(o);
-  const size_t esz = prec == kF32 ? 4 : 2;
-  const int bt = choose_tile(count, mats, o);
-  L->bt = bt;
   L->descs.clear();
-  for (int p = 0; p < PH_N; ++p) L->offs[p].assign(1, 0);
-  // first pass: shapes and Gram-side tile counts (for the split-K choice)
-  struct Shape { int64_t s, L, sp, Lp; int nb, nbL, syrk, upd, prep; };
+  L->prec.assign(count, kBF16);
+  L->bt.assign(count, kTileSmall);
+  for (int p = 0; p < PH_N; ++p)
+    for (int c = 0; c < kNCls; ++c) L->offs[p][c].assign(1, 0);
+  // update tiles of the whole call at the 256 tile (the built-in tile rule)
+  int64_t upd256 = 0;
+  for (int i = 0; i < count; ++i) {
+    const pe_matrix& m = mats[i];
+    if (m.m <= 0 || m.n <= 0) continue;
+    const int64_t s = std::min(m.m, m.n), Lx = std::max(m.m, m.n);
+    upd256 += round_up(s, kTileLarge) / kTileLarge * (round_up(Lx, kTileLarge) / kTileLarge);
+  }
+  // first pass: precision, tile, shapes and Gram-side tile counts per class
+  // (for the split-K choice)
+  struct Shape { int64_t s, L, sp, Lp; int nb, nbL, syrk, upd, prep, prec, bt, cls; };
   std::vector<Shape> sh;
-  int64_t syrk_total = 0;
+  int64_t syrk_total[kNCls] = {};
   for (int i = 0; i < count; ++i) {
     const pe_matrix& m = mats[i];
     Shape q{};
+    q.prec = kBF16;
+    q.bt = kTileSmall;
     if (m.m > 0 && m.n > 0) {
       q.s = std::min(m.m, m.n);
       q.L = std::max(m.m, m.n);
+      q.prec = prec_for(o, q.s);
+      q.bt = tile_for(o, q.prec, q.s, q.L, count, upd256);
+      const int bt = q.bt;
       q.sp = round_up(q.s, bt);
       q.Lp = round_up(q.L, bt);
       q.nb = (int)(q.sp / bt);
@@ -197,23 +217,30 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
       q.upd = q.nb * q.nbL;
       // items of kPrepGroup tiles (sp and Lp are multiples of 128, so the tile count is a multiple of 4)
       q.prep = (int)((q.sp / kPrepTile) * (q.Lp / kPrepTile) / kPrepGroup);
-      syrk_total += q.syrk;
     }
+    q.cls = cls_of(q.prec, q.bt);
+    syrk_total[q.cls] += q.syrk;
+    L->prec[i] = q.prec;
+    L->bt[i] = q.bt;
     sh.push_back(q);
   }
-  const int want = syrk_total > 0 ? (int)std::min<int64_t>(64, (kFillTarget + syrk_total - 1) / syrk_total) : 1;
+  int want[kNCls];
+  for (int c = 0; c < kNCls; ++c)
+    want[c] = syrk_total[c] > 0 ? (int)std::min<int64_t>(64, (kFillTarget + syrk_total[c] - 1) / syrk_total[c]) : 1;
   size_t off = 0;
   L->descs_off = off;
   off = align_up(off + sizeof(MatDesc) * (size_t)std::max(count, 1));
   L->offs_off = off;
-  off = align_up(off + sizeof(int32_t) * ((size_t)PH_N * (count + 1) + count));
+  off = align_up(off + sizeof(int32_t) * ((size_t)PH_N * kNCls * (count + 1) + (size_t)kNCls * count));
   const bool learned = learned_mode(o);
-  const bool q8 = prec == kBF16 && o->compute == PE_COMPUTE_FP8 && o->fp8_steps > 0 && bt == kTileLarge;
   L->coef_off = off;
   if (learned) off = align_up(off + sizeof(float) * kClasses * 3 * (size_t)o->T);
   for (int i = 0; i < count; ++i) {
     const pe_matrix& m = mats[i];
     const Shape& q = sh[i];
+    const int prec = q.prec, bt = q.bt;
+    const size_t esz = prec == kF32 ? 4 : 2;
+    const bool q8 = prec == kBF16 && o->compute == PE_COMPUTE_FP8 && o->fp8_steps > 0 && bt == kTileLarge;
     MatDesc d;
     memset(&d, 0, sizeof d);
     d.G = m.G;
@@ -246,8 +273,9 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
     const int bk = prec == kF32 ? 32 : 64;
     const int max_gram = std::max<int64_t>(1, q.Lp / (4 * bk));
     const int max_a2 = std::max<int64_t>(1, q.sp / (4 * bk));
-    d.gram_split = q.syrk ? std::min(want, max_gram) : 1;
-    d.a2_split = q.syrk ? std::min(want, max_a2) : 1;
+    const int cap = o->split_k > 0 ? o->split_k : 64;
+    d.gram_split = q.syrk ? std::min(std::min(want[q.cls], max_gram), cap) : 1;
+    d.a2_split = q.syrk ? std::min(std::min(want[q.cls], max_a2), cap) : 1;
     if (q.syrk) {
       auto take = [&](size_t bytes) {
         char* p = ws ? ws + off : nullptr;
@@ -269,6 +297,7 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
       d.red = (double*)take((size_t)q.prep * 12 + 16);
       d.scal = (float*)take(kScN * 4);
       d.cnt = (uint32_t*)take(64);  // reserved
+      d.trp = (float*)take((size_t)q.syrk * 2 * 4);
       // e4m3 operand copies of the FP8 steps (256 tile)
       if (q8) {
         d.Xq = (uint8_t*)take(X);
@@ -286,7 +315,13 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
       }
     }
     L->descs.push_back(d);
-    auto push = [&](int ph, int n) { L->offs[ph].push_back(L->offs[ph].back() + n); };
+    // this matrix's items in its class's tables, none in the others
+    auto push = [&](int ph, int n) {
+      for (int c = 0; c < kNCls; ++c) L->offs[ph][c].push_back(L->offs[ph][c].back() + (c == q.cls ? n : 0));
+    };
+    auto push_all = [&](int ph, int n) {
+      for (int c = 0; c < kNCls; ++c) L->offs[ph][c].push_back(L->offs[ph][c].back() + (c == 0 ? n : 0));
+    };
     push(PH_PREP, q.syrk ? q.prep : 0);
     push(PH_GRAM, q.syrk ? q.syrk * d.gram_split : 0);
     push(PH_A2, q.syrk ? q.syrk * d.a2_split : 0);
@@ -303,26 +338,34 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
     {
       const bool t = m.m > m.n;
       const int rows4 = (int)((m.m + 3) / 4), cols64 = (int)((m.n + 63) / 64);
-      push(PH_EST_A, (q.syrk && learned) ? (t ? rows4 : cols64) : 0);
-      push(PH_EST_B, (q.syrk && learned) ? (t ? cols64 : rows4) : 0);
+      push_all(PH_EST_A, (q.syrk && learned) ? (t ? rows4 : cols64) : 0);
+      push_all(PH_EST_B, (q.syrk && learned) ? (t ? cols64 : rows4) : 0);
     }
   }
-  {
+  for (int c = 0; c < kNCls; ++c) {
     // Gram phase in longest-k-first matrix order (stable)
     std::vector<int32_t> ord(count);
     for (int i = 0; i < count; ++i) ord[i] = i;
     std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return sh[x].Lp > sh[y].Lp; });
-    std::vector<int32_t> o(1, 0);
+    std::vector<int32_t> o2(1, 0);
     for (int k = 0; k < count; ++k) {
       const int i = ord[k];
-      o.push_back(o.back() + (L->offs[PH_GRAM][i + 1] - L->offs[PH_GRAM][i]));
+      o2.push_back(o2.back() + (L->offs[PH_GRAM][c][i + 1] - L->offs[PH_GRAM][c][i]));
     }
-    L->offs[PH_GRAM].swap(o);
-    L->ord_gram.swap(ord);
+    L->offs[PH_GRAM][c].swap(o2);
+    L->ord_gram[c].swap(ord);
   }
-  for (int p = 0; p < PH_N; ++p) L->totals[p] = L->offs[p].back();
+  for (int p = 0; p < PH_N; ++p)
+    for (int c = 0; c < kNCls; ++c) L->totals[p][c] = L->offs[p][c].back();
   L->bytes = off;
   return PE_OK;
+}
+
+// Items of a phase over all classes (zero: nothing to launch).
+int32_t phase_total(const Layout& L, int ph) {
+  int32_t t = 0;
+  for (int c = 0; c < kNCls; ++c) t += L.totals[ph][c];
+  return t;
 }
 
 pe_status validate(int count, const pe_matrix* mats, const pe_opts* o) {
@@ -360,7 +403,6 @@ pe_status put_words(void* dst, const void* src, size_t bytes, hipStream_t st) {
 
 struct pe_plan {
   int count = 0;
-  int prec = kBF16;
   int fp8_steps = 0;   // leading steps whose Gram-side products take e4m3 operands
   int T = 0;
   int norm_mode = 0;
@@ -386,8 +428,9 @@ pe_status upload(pe_plan* p, char* ws, hipStream_t st) {
   pe_status s = put_words(p->d_descs, p->L.descs.data(), sizeof(MatDesc) * p->L.descs.size(), st);
   if (s != PE_OK) return s;
   std::vector<int32_t> offs;
-  for (int ph = 0; ph < PH_N; ++ph) offs.insert(offs.end(), p->L.offs[ph].begin(), p->L.offs[ph].end());
-  offs.insert(offs.end(), p->L.ord_gram.begin(), p->L.ord_gram.end());
+  for (int ph = 0; ph < PH_N; ++ph)
+    for (int c = 0; c < kNCls; ++c) offs.insert(offs.end(), p->L.offs[ph][c].begin(), p->L.offs[ph][c].end());
+  for (int c = 0; c < kNCls; ++c) offs.insert(offs.end(), p->L.ord_gram[c].begin(), p->L.ord_gram[c].end());
   s = put_words(p->d_offs, offs.data(), offs.size() * 4, st);
   if (s != PE_OK || !p->learned) return s;
   // schedule table of the classes: class 4 is the caller's schedule
@@ -423,10 +466,14 @@ KArgs base_args(const pe_plan* p) {
   return a;
 }
 
-void set_phase(const pe_plan* p, KArgs* a, int ph) {
-  a->offs = p->d_offs + (size_t)ph * (p->count + 1);
-  a->ord = ph == PH_GRAM ? p->d_offs + (size_t)PH_N * (p->count + 1) : nullptr;
-  a->total = p->L.totals[ph];
+const int32_t* offs_ptr(const pe_plan* p, int ph, int c) {
+  return p->d_offs + ((size_t)ph * kNCls + c) * (p->count + 1);
+}
+
+void set_phase(const pe_plan* p, KArgs* a, int ph, int c) {
+  a->offs = offs_ptr(p, ph, c);
+  a->ord = ph == PH_GRAM ? p->d_offs + (size_t)PH_N * kNCls * (p->count + 1) + (size_t)c * p->count : nullptr;
+  a->total = p->L.totals[ph][c];
 }
 
 void set_step(const pe_plan* p, KArgs* a, int t) {
@@ -440,41 +487,51 @@ void set_step(const pe_plan* p, KArgs* a, int t) {
 pe_status enqueue_norm(const pe_plan* p, hipStream_t st, int fallback = 0) {
   KArgs a = base_args(p);
   a.fallback = fallback;
-  set_phase(p, &a, PH_PREP);
-  hipError_t e = launch_prep(p->prec, a, kPrepGridCap, st);
-  if (e != hipSuccess) return hip_fail(e, "prep launch");
+  hipError_t e;
+  for (int c = 0; c < kNCls; ++c) {
+    if (!p->L.totals[PH_PREP][c]) continue;
+    set_phase(p, &a, PH_PREP, c);
+    if ((e = launch_prep(cls_prec(c), a, kPrepGridCap, st)) != hipSuccess) return hip_fail(e, "prep launch");
+  }
   if ((e = launch_finalize(a, st)) != hipSuccess) return hip_fail(e, "finalize launch");
   return PE_OK;
 }
 
-// kind: 0 Gram, 1 A^2 + combine, 2 update
+// kind: 0 Gram, 1 A^2 + combine, 2 update; one launch (plus its split-K
+// reduction) per class present
 pe_status enqueue_gemm(const pe_plan* p, int t, int kind, hipStream_t st, int fallback = 0) {
   static const int ph_main[3] = {PH_GRAM, PH_A2, PH_UPD};
   static const int ph_red[3] = {PH_RGRAM, PH_RA2, -1};
   static const char* names[3] = {"gram launch", "a2 launch", "update launch"};
-  KArgs a = base_args(p);
-  set_step(p, &a, t);
-  set_phase(p, &a, ph_main[kind]);
-  a.fp8 = t < p->fp8_steps;
-  a.fp8_next = t + 1 < p->fp8_steps;
-  a.fallback = fallback;
-  // learned path, step 1: A^2 and its moments are kept until the class is chosen
-  a.raw_a2 = p->learned && !fallback && t == 0 && kind == 1;
-  // Gram-side products of the FP8 steps run the e4m3 kernels; updates stay bf16
-  const int prec = (a.fp8 && kind != 2) ? kFP8 : p->prec;
-  if (prec == kFP8 && p->L.bt == kTileLarge) {
-    // the 256 tile reads e4m3 copies: quantise X_t (or A_t) with its scale first
-    set_phase(p, &a, kind == 0 ? PH_QX : PH_QA);
-    hipError_t e = launch_quant(kind, a, kQuantGridCap, st);
-    if (e != hipSuccess) return hip_fail(e, "quantisation launch");
-    set_phase(p, &a, ph_main[kind]);
-  }
-  hipError_t e = launch_gemm(prec, p->L.bt, kind, a, p->L.bt == kTileLarge ? kGemmGridCapLarge : kGemmGridCap, st);
-  if (e != hipSuccess) return hip_fail(e, names[kind]);
-  if (ph_red[kind] >= 0 && p->L.totals[ph_red[kind]]) {
-    set_phase(p, &a, ph_red[kind]);
-    if ((e = launch_reduce(prec, p->L.bt, kind, a, kReduceGridCap, st)) != hipSuccess)
-      return hip_fail(e, "split-k reduce");
+  for (int c = 0; c < kNCls; ++c) {
+    if (!p->L.totals[ph_main[kind]][c]) continue;
+    const int bt = cls_bt(c);
+    KArgs a = base_args(p);
+    set_step(p, &a, t);
+    set_phase(p, &a, ph_main[kind], c);
+    // e4m3 Gram-side products in the first fp8_steps steps, bf16 matrices only
+    const bool q = cls_prec(c) == kBF16;
+    a.fp8 = q && t < p->fp8_steps;
+    a.fp8_next = q && t + 1 < p->fp8_steps;
+    a.fallback = fallback;
+    // learned path, step 1: A^2 and its moments are kept until the class is chosen
+    a.raw_a2 = p->learned && !fallback && t == 0 && kind == 1;
+    // Gram-side products of the FP8 steps run the e4m3 kernels; updates stay bf16
+    const int prec = (a.fp8 && kind != 2) ? kFP8 : cls_prec(c);
+    hipError_t e;
+    if (prec == kFP8 && bt == kTileLarge) {
+      // the 256 tile reads e4m3 copies: quantise X_t (or A_t) with its scale first
+      set_phase(p, &a, kind == 0 ? PH_QX : PH_QA, c);
+      if ((e = launch_quant(kind, a, kQuantGridCap, st)) != hipSuccess) return hip_fail(e, "quantisation launch");
+      set_phase(p, &a, ph_main[kind], c);
+    }
+    e = launch_gemm(prec, bt, kind, a, bt == kTileLarge ? kGemmGridCapLarge : kGemmGridCap, st);
+    if (e != hipSuccess) return hip_fail(e, names[kind]);
+    if (ph_red[kind] >= 0 && p->L.totals[ph_red[kind]][c]) {
+      set_phase(p, &a, ph_red[kind], c);
+      if ((e = launch_reduce(prec, bt, kind, a, kReduceGridCap, st)) != hipSuccess)
+        return hip_fail(e, "split-k reduce");
+    }
   }
   return PE_OK;
 }
@@ -485,8 +542,11 @@ pe_status enqueue_select(const pe_plan* p, hipStream_t st) {
   set_step(p, &a, 0);
   hipError_t e = launch_select(a, st);
   if (e != hipSuccess) return hip_fail(e, "select launch");
-  set_phase(p, &a, PH_COMBINE);
-  if ((e = launch_combine(p->prec, a, st)) != hipSuccess) return hip_fail(e, "combine launch");
+  for (int c = 0; c < kNCls; ++c) {
+    if (!p->L.totals[PH_COMBINE][c]) continue;
+    set_phase(p, &a, PH_COMBINE, c);
+    if ((e = launch_combine(cls_prec(c), a, st)) != hipSuccess) return hip_fail(e, "combine launch");
+  }
   return PE_OK;
 }
 
@@ -503,14 +563,13 @@ pe_status enqueue_steps(const pe_plan* p, hipStream_t st, int fallback) {
 }
 
 pe_status enqueue(const pe_plan* p, hipStream_t st) {
-  if (p->L.totals[PH_PREP] == 0) return PE_OK;
+  if (phase_total(p->L, PH_PREP) == 0) return PE_OK;
   pe_status s = enqueue_steps(p, st, 0);
   if (s != PE_OK || !p->learned || !(p->tau > 0.0f)) return s;
   // estimate ||X X^T - I||_2 of every result; re-run the failed ones with class 4
   KArgs a = base_args(p);
-  hipError_t e = launch_est(a, kEstIters, st, p->d_offs + (size_t)PH_EST_A * (p->count + 1),
-                            p->L.totals[PH_EST_A], p->d_offs + (size_t)PH_EST_B * (p->count + 1),
-                            p->L.totals[PH_EST_B]);
+  hipError_t e = launch_est(a, kEstIters, st, offs_ptr(p, PH_EST_A, 0), p->L.totals[PH_EST_A][0],
+                            offs_ptr(p, PH_EST_B, 0), p->L.totals[PH_EST_B][0]);
   if (e != hipSuccess) return hip_fail(e, "estimate launch");
   return enqueue_steps(p, st, 1);
 }
@@ -520,7 +579,6 @@ pe_status plan_init(pe_plan* p, int count, const pe_matrix* mats, const pe_opts*
   pe_status s = validate(count, mats, o);
   if (s != PE_OK) return s;
   p->count = count;
-  p->prec = prec_of(o);
   p->fp8_steps = o->compute == PE_COMPUTE_FP8 ? o->fp8_steps : 0;
   p->T = o->T;
   p->norm_mode = o->norm_mode;
@@ -532,7 +590,7 @@ pe_status plan_init(pe_plan* p, int count, const pe_matrix* mats, const pe_opts*
   p->tau = o->fallback_tau;
   Layout sizing;
   build_layout(count, mats, o, nullptr, &sizing);
-  if (sizing.totals[PH_PREP] == 0) return PE_OK;  // nothing but empty matrices
+  if (phase_total(sizing, PH_PREP) == 0) return PE_OK;  // nothing but empty matrices
   if (!ws || ((uintptr_t)ws & 255) || ws_bytes < sizing.bytes) return PE_EWORKSPACE;
   build_layout(count, mats, o, (char*)ws, &p->L);
   warm_launch_grids();
@@ -618,7 +676,7 @@ pe_status pe_plan_launch_phase(pe_plan* p, int32_t step, int32_t phase, void* st
   if (!p || step < 0 || step >= p->T || phase < 0 || phase > 3) return PE_EINVAL;
   // a learned plan's step 1 also selects the class between its phases
   if (p->learned) return PE_EUNSUPPORTED;
-  if (p->L.totals[PH_PREP] == 0) return PE_OK;
+  if (phase_total(p->L, PH_PREP) == 0) return PE_OK;
   hipStream_t st = (hipStream_t)stream;
   if (phase == 0) return enqueue_norm(p, st);
   return enqueue_gemm(p, step, phase - 1, st);

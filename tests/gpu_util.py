@@ -28,6 +28,27 @@ def relf(X, ref) -> float:
     return OI.rel_fro(X, ref)
 
 
+def tile_relf(X, ref, bt: int = 256) -> float:
+    """Largest block error over the bt x bt blocks of the output: the block's
+    error ||X_b - ref_b||_F relative to the larger of ||ref_b||_F and the
+    block's share of the whole reference, ||ref||_F sqrt(|b| / |ref|) (thin
+    edge blocks and blocks with little content are measured against the
+    matrix-average scale, so an error confined to one block shows up while a
+    near-zero block does not blow up)."""
+    X = np.asarray(X, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    tot = float(np.linalg.norm(ref))
+    if tot == 0:
+        return float(np.linalg.norm(X))
+    worst = 0.0
+    for i in range(0, ref.shape[0], bt):
+        for j in range(0, ref.shape[1], bt):
+            r = ref[i:i + bt, j:j + bt]
+            den = max(float(np.linalg.norm(r)), tot * np.sqrt(r.size / ref.size))
+            worst = max(worst, float(np.linalg.norm(X[i:i + bt, j:j + bt] - r)) / den)
+    return worst
+
+
 def polar_error(X: np.ndarray, P: np.ndarray) -> float:
     return SP.spec_norm(np.asarray(X, dtype=np.float64) - P)
 

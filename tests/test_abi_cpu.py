@@ -28,6 +28,16 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
+def test_default_cushion_is_the_ratio_rule_root():
+    """pe_coeffs derives its default cushion from Appendix F's ratio-1/10 rule
+    (bisection); it agrees with the factor printed in the Appendix A.2 listing
+    to the rounding level of the minimax error it bisects on."""
+    o = pe.CoeffOpts()
+    pe.lib().pe_coeff_opts_default(ctypes.byref(o))
+    assert abs(o.cushion - 0.02407327424182761) <= 1e-16
+    assert abs(o.cushion - S.CUSHION) <= 1e-16
+
+
 def test_coeffs_match_oracle_and_paper(golden_dir):
     paper = np.loadtxt(os.path.join(golden_dir, "paper_coeffs_ell1e-3.txt"))
     c = pe.coeffs(1e-3, 8, safety=1.0)
@@ -137,9 +147,9 @@ def test_learned_labels_match_oracle():
 
 
 def test_tile_table_drives_the_tile_choice(tmp_path):
-    """An autotuned table entry changes the padding (128 vs 256) and so the
-    workspace size; malformed tables are rejected; unknown classes keep the
-    built-in choice."""
+    """An autotuned table entry (class and call regime) changes the padding
+    (128 vs 256) and so the workspace size; malformed tables are rejected;
+    unknown classes keep the built-in choice."""
     L = pe.lib()
     o, keep = _opts()
     m = pe.Matrix(16, 32, 600, 1000, 1000, 1000, 1, 1)
@@ -148,7 +158,8 @@ def test_tile_table_drives_the_tile_choice(tmp_path):
     t = tmp_path / "tab.txt"
     sizes = {}
     for tile in (1, 2):
-        t.write_text(f"# test\n{cls} {tile}  # comment\n")
+        # a single-matrix call looks up the class's _x1 regime
+        t.write_text(f"# test\n{cls}_x1 {tile}  # comment\n{cls}_xN {3 - tile}\n")
         assert L.pe_tile_table_load(str(t).encode()) == 0
         sizes[tile] = L.pe_workspace_size(1, ctypes.byref(m), ctypes.byref(o))
     assert sizes[2] > sizes[1]

@@ -2,16 +2,18 @@
 
 Bars: relative Frobenius error to the FP64 same iteration on the same input
 values <= 1e-5 for the FP32 path and <= 3e-2 for the bf16 path (FP32 master,
-bf16 MFMA operands); the polar error ||X_T - U V^T||_2 is reported where U V^T
-is known by construction.  Shapes span several 128-wide tiles, ragged tails,
-both orientations, split-K and grouped (batched) launches.
+bf16 MFMA operands), for the whole matrix and for every 256 x 256 block of the
+output; the polar error ||X_T - U V^T||_2 is reported where U V^T is known by
+construction.  Shapes span several 128-wide tiles, ragged tails, both
+orientations, split-K and unsplit Gram-side products, and grouped (batched)
+launches.
 """
 import numpy as np
 import pytest
 
 import synth
 from tests.gpu_util import (device_input, oracle_same_iteration, oracle_schedule, polar_error,
-                            relf, to_np)
+                            relf, tile_relf, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -32,29 +34,20 @@ def pe():
     return pe
 
 
-def bf16_bar(vals, abc, ref):
-    """3e-2, or 1.25x the distance that bf16 operand rounding alone puts between
-    a float64 model of the bf16 path and the FP64 iteration, if that is larger
-    (inputs whose singular values sit where a step is non-monotone)."""
-    from oracle.lowprec import iteration_bf16_operands
-    e_model = relf(iteration_bf16_operands(vals, abc), ref)
-    return max(TOL["bf16"], 1.25 * e_model), e_model
-
-
 def _check(pe, torch, G64, T, compute, dtype, tol=None, **kw):
     G, vals = device_input(G64, dtype)
     abc = oracle_schedule(T)
     X = pe.polar(G, T=T, abc=abc, compute=compute, out_dtype=torch.float32, **kw)
     torch.cuda.synchronize()
     ref = oracle_same_iteration(vals, abc)
-    err = relf(to_np(X), ref)
+    Xn = to_np(X)
+    err, terr = relf(Xn, ref), tile_relf(Xn, ref)
     bar = tol if tol is not None else TOL[compute]
-    if tol is None and compute == "bf16":
-        bar, e_model = bf16_bar(vals, abc, ref)
-        print(f"[parity] bf16 rounding model relF={e_model:.3e}", flush=True)
-    print(f"[parity] shape={G64.shape} compute={compute} T={T} relF={err:.3e} bar={bar}", flush=True)
+    print(f"[parity] shape={G64.shape} compute={compute} T={T} {kw} relF={err:.3e} "
+          f"max-block relF={terr:.3e} bar={bar}", flush=True)
     assert np.isfinite(err) and err <= bar, err
-    return to_np(X), ref
+    assert terr <= bar, terr
+    return Xn, ref
 
 
 def test_config1_fp32_gaussian_256(pe, torch_cuda):
@@ -76,20 +69,59 @@ def test_ragged_shapes_f32_gaussian(pe, torch_cuda, shape):
 
 
 @pytest.mark.parametrize("shape", RAGGED)
+def test_ragged_shapes_bf16_gaussian(pe, torch_cuda, shape):
+    """iid N(0,1) inputs: the singular values sit close together, the case
+    where an unshifted bf16 update product loses most accuracy."""
+    r = synth.rng(500 + shape[0] * 3 + shape[1])
+    _check(pe, torch_cuda, r.standard_normal(shape), 5, "bf16", torch_cuda.bfloat16)
+
+
+@pytest.mark.parametrize("shape", RAGGED)
 def test_ragged_shapes_bf16_powerlaw(pe, torch_cuda, shape):
     """Gradient-like inputs (sigma_i = 1/i, Haar singular vectors)."""
     G64 = synth.powerlaw(500 + shape[0] * 3 + shape[1], shape[0], shape[1]).G
     _check(pe, torch_cuda, G64, 5, "bf16", torch_cuda.bfloat16)
 
 
-def test_bf16_narrow_spectrum_gaussian(pe, torch_cuda):
-    """A wide Gaussian matrix has all normalised singular values in a narrow band
-    [0.056, 0.12]; steps 2-3 of the l = 1e-3 schedule then map values near u_t
-    down to l_{t+1} (p(x)/x ~ 0.11, the non-monotone case of Appendix F), which
-    amplifies the bf16 operand rounding: the float64 model of the rounding points
-    alone is 3.45e-2 from the FP64 iteration, so the bar is 1.25x that."""
-    G64 = synth.rng(1).standard_normal((130, 1000))
+@pytest.mark.parametrize("shape", [(130, 1000), (64, 4096), (512, 2048)])
+def test_bf16_narrow_spectrum_gaussian(pe, torch_cuda, shape):
+    """Wide Gaussian matrices: every normalised singular value in a narrow band
+    (130 x 1000: [0.056, 0.12]); steps 2-3 of the l = 1e-3 schedule map values
+    near u_t down by p(x)/x ~ 0.11 (the non-monotone case of Appendix F)."""
+    G64 = synth.rng(shape[0] + 1).standard_normal(shape)
     _check(pe, torch_cuda, G64, 5, "bf16", torch_cuda.bfloat16)
+
+
+def test_bf16_orthogonal_input(pe, torch_cuda):
+    """All singular values equal (Haar orthogonal 384 x 384)."""
+    Q = synth.haar(synth.rng(606), 384, 384)
+    _check(pe, torch_cuda, Q, 5, "bf16", torch_cuda.bfloat16)
+
+
+@pytest.mark.parametrize("centres", [1, 2, 4])
+def test_bf16_clustered_spectrum(pe, torch_cuda, centres):
+    """Singular values in 1-4 tight clusters (+-10%) with log-uniform centres."""
+    r = synth.rng(607 + centres)
+    sig = synth.spectrum_clustered(r, 300, centres, lo=1e-3)
+    _check(pe, torch_cuda, synth.usv(r, 300, 900, sig).G, 5, "bf16", torch_cuda.bfloat16)
+
+
+@pytest.mark.parametrize("shape", [(200, 600), (600, 200)])
+def test_bf16_rank_one(pe, torch_cuda, shape):
+    """Rank one with Gaussian factors: the iterate stays rank one and the
+    other singular values stay exactly zero."""
+    r = synth.rng(610 + shape[0])
+    G64 = np.outer(r.standard_normal(shape[0]), r.standard_normal(shape[1]))
+    _check(pe, torch_cuda, G64, 5, "bf16", torch_cuda.bfloat16)
+
+
+@pytest.mark.xfail(strict=True, reason=(
+    "excluded input class of the bf16 path: identical rows on the smaller side "
+    "(here a constant matrix), so every entry of B = bA + cA^2 is the same "
+    "number and its bf16 rounding is one systematic relative error of up to "
+    "2^-9 instead of independent ones; steps 2-3 amplify it ~20x"))
+def test_bf16_constant_matrix_excluded(pe, torch_cuda):
+    _check(pe, torch_cuda, np.ones((200, 600)), 5, "bf16", torch_cuda.bfloat16)
 
 
 @pytest.mark.parametrize("compute", ["f32", "bf16"])
@@ -169,9 +201,8 @@ def test_batched_uneven(pe, torch_cuda):
     for X, v, s in zip(Xs, vals, shapes):
         ref = oracle_same_iteration(v, abc)
         err = relf(to_np(X), ref)
-        bar, e_model = bf16_bar(v, abc, ref)
-        print(f"[batched] {s} relF={err:.3e} bf16-model={e_model:.3e}", flush=True)
-        assert err <= bar
+        print(f"[batched] {s} relF={err:.3e}", flush=True)
+        assert err <= TOL["bf16"]
     # the grouped path computes each matrix exactly as the single path does
     for G, X in zip(Gs[:3], Xs[:3]):
         Y = pe.polar(G, T=5, abc=abc, compute="bf16", out_dtype=torch_cuda.float32)
@@ -262,3 +293,83 @@ def test_large_tile_bf16_output_equals_rounded_fp32(pe, torch_cuda, shape):
     assert torch.equal(X16, ref)
     assert torch.equal(Xs, ref)
     assert torch.count_nonzero(big[:, shape[1]:]) == 0   # nothing written past the columns
+
+
+@pytest.mark.parametrize("compute", ["bf16", "fp8"])
+@pytest.mark.parametrize("shape", [(768, 2304), (1300, 700)])
+def test_large_tile_unsplit(pe, torch_cuda, shape, compute):
+    """split_k = 1 on the 256 tile: off-diagonal Gram and A^2 tiles leave LDS
+    through the staged epilogue (mirror rows, then the tile's own rows gathered
+    with transposing reads), the path of every Gram and A^2 launch of large
+    batches; the split-K result of the same call agrees to summation order."""
+    G64 = synth.powerlaw(1400 + shape[0], *shape).G
+    G, vals = device_input(G64, torch_cuda.bfloat16)
+    abc = oracle_schedule(5)
+    kw = dict(T=5, abc=abc, compute=compute, out_dtype=torch_cuda.float32, tile=2,
+              fp8_steps=3 if compute == "fp8" else 0)
+    X1 = pe.polar(G, split_k=1, **kw)
+    Xs = pe.polar(G, **kw)
+    torch_cuda.cuda.synchronize()
+    ref = oracle_same_iteration(vals, abc)
+    e1, es = relf(to_np(X1), ref), relf(to_np(Xs), ref)
+    t1 = tile_relf(to_np(X1), ref)
+    d = relf(to_np(X1), to_np(Xs))
+    print(f"[unsplit] {shape} {compute} relF unsplit={e1:.3e} (max block {t1:.3e}) "
+          f"split={es:.3e} unsplit-vs-split={d:.3e}", flush=True)
+    assert e1 <= 3e-2 and t1 <= 3e-2 and es <= 3e-2
+    assert d <= 1e-2
+
+
+def test_split_k_option_rejects_out_of_range(pe, torch_cuda):
+    G = torch_cuda.ones((64, 64), device="cuda")
+    with pytest.raises(pe.PEError):
+        pe.polar(G, T=5, split_k=65)
+
+
+def test_tiny_matrices_run_fp32_operands(pe, torch_cuda):
+    """s < 16: a bf16 call runs the FP32 kernels (a handful of singular values
+    leaves bf16 rounding nothing to average over), bit for bit the FP32 call."""
+    for shape in [(7, 3), (3, 7), (15, 40), (40, 15)]:
+        G64 = synth.rng(620 + shape[0]).standard_normal(shape)
+        G, vals = device_input(G64, torch_cuda.float32)
+        abc = oracle_schedule(5)
+        Xb = pe.polar(G, T=5, abc=abc, compute="bf16", out_dtype=torch_cuda.float32)
+        Xf = pe.polar(G, T=5, abc=abc, compute="f32", out_dtype=torch_cuda.float32)
+        torch_cuda.cuda.synchronize()
+        assert torch_cuda.equal(Xb, Xf), shape
+        assert relf(to_np(Xb), oracle_same_iteration(vals, abc)) <= 1e-5
+
+
+def test_mixed_classes_in_one_call(pe, torch_cuda, tmp_path):
+    """One grouped call whose matrices take different block tiles (from a
+    table loaded for the test) and precisions: each phase launches once per
+    (precision, tile) class; every matrix matches the FP64 oracle and its own
+    single call with the same tile."""
+    import paper_2505_16932_amd as pkg
+    L = pe.lib()
+    table = tmp_path / "tiles.txt"
+    table.write_text("bf16_s512_a4_xN 2\nbf16_s1024_a1_xN 1\nbf16_s512_a1_xN 1\n")
+    shapes = [(512, 1536), (1024, 1024), (7, 30), (1536, 512), (300, 300)]
+    tiles = [2, 1, 1, 2, 1]
+    Gs, vals = [], []
+    for k, sh in enumerate(shapes):
+        g, v = device_input(synth.powerlaw(640 + k, *sh).G, torch_cuda.bfloat16)
+        Gs.append(g)
+        vals.append(v)
+    abc = oracle_schedule(5)
+    try:
+        assert L.pe_tile_table_load(str(table).encode()) == 0
+        Xs = pe.polar_batched(Gs, T=5, abc=abc, compute="bf16", out_dtype=torch_cuda.float32)
+        torch_cuda.cuda.synchronize()
+    finally:
+        default = pkg.os.path.join(pkg.HERE, "tile_table.txt")
+        assert L.pe_tile_table_load(default.encode()) == 0
+    for X, G, v, sh, t in zip(Xs, Gs, vals, shapes, tiles):
+        ref = oracle_same_iteration(v, abc)
+        e = relf(to_np(X), ref)
+        Y = pe.polar(G, T=5, abc=abc, compute="bf16", out_dtype=torch_cuda.float32, tile=t)
+        torch_cuda.cuda.synchronize()
+        d = relf(to_np(X), to_np(Y))
+        print(f"[mixed] {sh} tile={t} relF={e:.3e} vs single call {d:.3e}", flush=True)
+        assert e <= 3e-2
+        assert d <= 2e-3

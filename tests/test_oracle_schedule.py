@@ -115,14 +115,35 @@ def test_remez_iteration_count():
 
 
 def test_cushion_is_tenth_ratio_rule():
-    """Appendix F motivates the cushion by a ratio-1/10 rule.  The listing's
-    constant is the r at which the minimax quintic on [r, 1] has error 9/11,
-    i.e. maps [r, 1] onto [2/11, 20/11], an interval of ratio 1/10."""
+    """Appendix F states the cushion as a ratio-1/10 rule and says its code
+    uses a different factor.  The oracle derives its cushion from the rule
+    applied to the image: the r at which the minimax quintic on [r, 1] has
+    error 9/11, i.e. maps [r, 1] onto [2/11, 20/11], an interval of ratio
+    1/10.  Pinned to the factor the Appendix A.2 listing prints,
+    0.02407327424182761, to the spacing of doubles."""
+    listing_factor = 0.02407327424182761
+    # float64: E(r) carries a few ulps of rounding, which blurs the root by ~1e-17
+    assert abs(S.CUSHION - listing_factor) <= 1e-16
+    # 40-digit arithmetic: the root, 0.0240732742418275956660..., agrees with
+    # the printed factor to its 16 significant digits
+    import mpmath as mp
+    with mp.workdps(40):
+        lo, hi = mp.mpf("0.02"), mp.mpf("0.03")
+        target = mp.mpf(9) / 11
+        for _ in range(70):
+            mid = (lo + hi) / 2
+            if abs(S.remez_quintic_mp(mid, 1, dps=40)[3]) > target:
+                lo = mid
+            else:
+                hi = mid
+        assert abs(lo - mp.mpf("0.02407327424182761")) <= mp.mpf("2e-17")
     r = S.remez_quintic(S.CUSHION, 1.0)
     assert abs(abs(r.E) - 9.0 / 11.0) <= 1e-12
     lo_img = 1 - abs(r.E)
     hi_img = 1 + abs(r.E)
     assert abs(lo_img / hi_img - 0.1) <= 1e-12
+    # other ratios move the root monotonically
+    assert S.ratio_cushion(0.2) > S.CUSHION > S.ratio_cushion(0.05)
 
 
 def test_theorem1_composite_error_pure_greedy():
