@@ -150,6 +150,21 @@ size_t pe_workspace_size(int32_t count, const pe_matrix* mats, const pe_opts* op
 pe_status pe_polar(const pe_matrix* mat, const pe_opts* opts, void* ws, size_t ws_bytes,
                    void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): pe_polar
+ * with the workspace taken from a static device array of
+ * PE_NOALLOC_SCRATCH_BYTES inside the library (one per device, allocated when
+ * the library's code object is loaded on that device and held until the
+ * process ends).  The caller still owns G and X.  Same kernels, workspace
+ * layout and results as pe_polar.  Returns PE_EWORKSPACE (message in
+ * pe_last_error) when the matrix needs more workspace than the array holds
+ * (pe_workspace_size tells), and otherwise what pe_polar returns.  Every call
+ * on one device shares that device's array, so calls that overlap on a device
+ * (different streams or threads without ordering) race; calls ordered on one
+ * stream do not.  No hipMalloc, hipFree or other allocating call is made. */
+#define PE_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+pe_status pe_polar_noalloc(const pe_matrix* mat, const pe_opts* opts, void* stream);
+
 /* A list of matrices of uneven shapes in grouped launches: each phase (norm,
  * Gram, A^2 + combine, update) is one persistent launch over the tiles of all
  * matrices.  The tile tables are written into the workspace by small kernels

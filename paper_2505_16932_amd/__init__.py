@@ -21,7 +21,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["coeffs", "polar", "polar_batched", "Plan", "workspace_size", "lib", "PEError",
+__all__ = ["coeffs", "polar", "polar_batched", "polar_noalloc", "Plan", "workspace_size", "lib", "PEError",
            "COMPUTE", "LIB_PATH"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -93,6 +93,8 @@ def lib() -> ctypes.CDLL:
         L.pe_polar.restype = ctypes.c_int
         L.pe_polar.argtypes = [ctypes.POINTER(Matrix), ctypes.POINTER(Opts), ctypes.c_void_p,
                                ctypes.c_size_t, ctypes.c_void_p]
+        L.pe_polar_noalloc.restype = ctypes.c_int
+        L.pe_polar_noalloc.argtypes = [ctypes.POINTER(Matrix), ctypes.POINTER(Opts), ctypes.c_void_p]
         L.pe_polar_batched.restype = ctypes.c_int
         L.pe_polar_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(Matrix), ctypes.POINTER(Opts),
                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
@@ -353,6 +355,23 @@ def polar_batched(Gs, T: int = 5, ell: float = 1e-3, abc=None, compute: str = "b
         # keep the workspace alive until the stream has consumed it
         ws_buf.record_stream(torch.cuda.current_stream() if stream is None else stream)
     return outs
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def polar_noalloc(G, out, T: int = 5, ell: float = 1e-3, abc=None, compute: str = "bf16",
+                  fp8_steps: int = 0, norm_mode: int = 0, tile: int = 0, split_k: int = 0,
+                  stream=None):
+    """X_T for one matrix into the caller's ``out`` with the library's static
+    workspace (pe_polar_noalloc: no device allocation by the library or here)."""
+    sched = _schedule(T, ell, abc)
+    o, _keep = _opts(T, sched, compute, fp8_steps, norm_mode, tile, split_k=split_k)
+    mat = _matrix(G, out)
+    L = lib()
+    _check(L.pe_polar_noalloc(ctypes.byref(mat), ctypes.byref(o), _stream(stream)),
+           "pe_polar_noalloc")
+    return out
 
 
 def quantize_e4m3(x, scale: float, stream=None):

@@ -599,6 +599,40 @@ pe_status plan_init(pe_plan* p, int count, const pe_matrix* mats, const pe_opts*
 
 }  // namespace
 
+// ------------------------------------------------ allocation-free entry point
+// pe_polar_noalloc keeps its workspace in this file-scope device array instead
+// of the caller's: one copy per device, allocated when the code object is
+// loaded there and held until the process ends.  In host code `scratch` is
+// only a stand-in for the symbol; its device address comes from
+// hipGetSymbolAddress, queried once per device (with that device current) and
+// cached.
+static __device__ __align__(256) char scratch[PE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+pe_status scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) {
+    g_last_error = "device index beyond the scratch table";
+    return PE_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PE_OK;
+}
+}  // namespace
+
 // ----------------------------------------------------------------- C ABI
 extern "C" {
 
@@ -622,6 +656,25 @@ pe_status pe_polar_batched(int32_t count, const pe_matrix* mats, const pe_opts* 
 pe_status pe_polar(const pe_matrix* mat, const pe_opts* opts, void* ws, size_t ws_bytes, void* stream) {
   if (!mat) return PE_EINVAL;
   return pe_polar_batched(1, mat, opts, ws, ws_bytes, stream);
+}
+
+pe_status pe_polar_noalloc(const pe_matrix* mat, const pe_opts* opts, void* stream) {
+  g_last_error.clear();
+  if (!mat) return PE_EINVAL;
+  pe_status s = validate(1, mat, opts);
+  if (s != PE_OK) return s;
+  Layout sizing;
+  build_layout(1, mat, opts, nullptr, &sizing);
+  if (sizing.bytes > (size_t)PE_NOALLOC_SCRATCH_BYTES) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "pe_polar_noalloc: this matrix needs %zu bytes of workspace, the static "
+             "scratch holds %zu", sizing.bytes, (size_t)PE_NOALLOC_SCRATCH_BYTES);
+    g_last_error = buf;
+    return PE_EWORKSPACE;
+  }
+  void* ws = nullptr;
+  if ((s = scratch_address(&ws)) != PE_OK) return s;
+  return pe_polar(mat, opts, ws, (size_t)PE_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 pe_status pe_plan_create(int32_t count, const pe_matrix* mats, const pe_opts* opts, void* ws,
