@@ -20,6 +20,11 @@ Contents (each function cites the passage of the paper it follows):
   matrix error to the scalar composite on the spectrum.
 * ``lowprec``   -- round-to-nearest-even bfloat16 / OCP e4m3 quantisers used to
   state what the low-precision paths compute.
+* ``fastapply`` -- Algorithm 4 (Appendix G): the composite as Q X with Q a
+  polynomial in the Gram matrix, restarted every k steps, first-segment shift.
+* ``muon``      -- one Muon optimizer step (Section 1.1) around the iteration.
+* ``spectral_init`` -- the spectrum-aware initialisation step for a large
+  outlying singular value (appendix on large spectral gaps, k = 1).
 * ``mlp``       -- FP64 forward/backward/update of the small l-predictor MLP
   and its spectrum-level labels.
 

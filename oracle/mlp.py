@@ -2,16 +2,20 @@
 
 The paper fixes l = 1e-3 because a good lower bound on sigma_min is hard to
 get cheaply and a wrong guess only costs a few iterations (Section 3.3).  The
-predictor picks one of eight precomputed schedules (l in CLASS_ELL) per matrix
-from moments of the step-1 Gram matrix A = X_0 X_0^T:
+predictor picks one of eight precomputed schedules per matrix from moments of
+the step-1 Gram matrix A = X_0 X_0^T:
     m_k = tr(A^k) = sum_i sigma_hat_i^(2k),  k = 1..4,
-which the GPU path accumulates from A (k = 1, 2) and A^2 (k = 3, 4).
+which the GPU path accumulates from A (k = 1, 2) and A^2 (k = 3, 4).  A class
+is a pair (l, T'): the greedy schedule for l run for T' <= T steps (steps past
+T' leave X as it is), so a matrix whose spectrum allows it finishes early.
 
 * ``features``: the 16 inputs, from (s, L, m_1..m_4).
 * ``moments_from_spectrum``: m_k from the normalised singular values.
-* ``class_errors``: the Appendix C identity -- the polar error of schedule c
-  after T steps is max_i |1 - phi_T^c(sigma_hat_i)| -- so labels need only the
-  spectrum (argmin over classes, ties to the larger l).
+* ``class_errors``: the Appendix C identity -- the polar error of class c is
+  max_i |1 - phi^c(sigma_hat_i)| for its T'-step composite phi^c -- so labels
+  need only the spectrum.
+* ``label``: the class with the fewest steps whose error does not exceed the
+  fixed class's (l = 1e-3, T steps); among those the smallest error.
 * ``forward`` / ``backward`` / ``adam``: the MLP 16 -> 64 -> 64 -> 8 with ReLU
   hidden layers and softmax cross-entropy, in float64.
 
@@ -24,8 +28,12 @@ import numpy as np
 
 from .schedule import composite, greedy_schedule
 
-CLASS_ELL = np.array([1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5])
-FIXED_CLASS = 4  # l = 1e-3, the paper's choice
+# (l, T') per class; T' = None means the call's T.  Class 4 is the paper's
+# choice, l = 1e-3 for all T steps.
+CLASS_TABLE = [(1e-1, 2), (1e-1, 3), (3e-2, 3), (1e-2, 4), (1e-3, None), (3e-3, 4), (3e-4, None),
+               (1e-4, None)]
+CLASS_ELL = np.array([c[0] for c in CLASS_TABLE])
+FIXED_CLASS = 4
 N_IN, N_H, N_OUT = 16, 64, 8
 SHAPES = [(N_IN, N_H), (N_H,), (N_H, N_H), (N_H,), (N_H, N_OUT), (N_OUT,)]
 N_PARAMS = sum(int(np.prod(s)) for s in SHAPES)
@@ -71,22 +79,34 @@ def features(s, L, m):
     ])
 
 
+def class_steps(T):
+    """T' of every class for a T-step call."""
+    return np.array([min(T, k) if k is not None else T for _, k in CLASS_TABLE])
+
+
 def class_schedules(T, safety=1.01):
-    return [greedy_schedule(float(l), T, safety=safety).abc for l in CLASS_ELL]
+    """Each class's T'-step greedy schedule (a list of (T', 3) arrays)."""
+    return [greedy_schedule(float(l), int(k), safety=safety).abc
+            for (l, _), k in zip(CLASS_TABLE, class_steps(T))]
 
 
 def class_errors(sigma_hat, T, scheds=None):
-    """Polar error of each class's T-step schedule (Appendix C identity)."""
+    """Polar error of each class's schedule (Appendix C identity)."""
     scheds = scheds or class_schedules(T)
     x = np.asarray(sigma_hat, dtype=np.float64)
     return np.array([np.max(np.abs(1.0 - composite(abc, x))) for abc in scheds])
 
 
-def label(errs, rtol=1e-9):
-    """argmin over classes; ties (within rtol) go to the larger l (smaller index)."""
+def label(errs, steps, rtol=1e-9):
+    """Fewest steps among the classes whose error is within the fixed class's
+    (rtol, plus 1e-15 absolute); ties to the smaller error, then the smaller
+    index."""
     errs = np.asarray(errs)
-    best = np.min(errs)
-    return int(np.flatnonzero(errs <= best * (1 + rtol) + 1e-15)[0])
+    steps = np.asarray(steps)
+    ok = np.flatnonzero(errs <= errs[FIXED_CLASS] * (1 + rtol) + 1e-15)
+    fewest = steps[ok].min()
+    cand = ok[steps[ok] == fewest]
+    return int(cand[np.argmin(errs[cand])])
 
 
 def forward(theta, X):

@@ -216,6 +216,36 @@ def greedy_schedule(ell: float, T: int, cushion: float = CUSHION, recentre: bool
                     np.array(degen), np.array(iters))
 
 
+def greedy_schedule_cubic(ell: float, T: int, safety: float = SAFETY,
+                          safety_on_last: bool = True) -> Schedule:
+    """The greedy composition of Theorem 1 for degree 3: each p_t is the
+    closed-form minimax cubic of eq. (deg3_solution) on [l_t, u_t]; its error
+    equioscillates at l_t, 1/alpha and u_t, so the image is [1 - E, 1 + E]
+    and l_{t+1} = 1 - E, u_{t+1} = 1 + E = 2 - l_{t+1} (eq. newbounds).  No
+    cushion (every interval's cubic has p(x)/x decreasing on [0, u_t], so no
+    value is pulled below the next lower bound); the safety factor of
+    Appendix F as for degree 5.  Coefficients as (a, b, 0) triples."""
+    if not (0.0 < ell < 1.0) or T < 1:
+        raise ValueError("need 0 < ell < 1 and T >= 1")
+    l_t, u_t = float(ell), 1.0
+    ells, us, unsafe = [l_t], [u_t], []
+    for _ in range(T):
+        a, b, E = cubic_closed_form(l_t, u_t)
+        unsafe.append((a, b, 0.0))
+        l_t = float(eval_odd_quintic((a, b, 0.0), l_t))
+        u_t = 2.0 - l_t
+        ells.append(l_t)
+        us.append(u_t)
+    safe = []
+    for t, abc in enumerate(unsafe):
+        if safety != 1.0 and (safety_on_last or t < T - 1):
+            abc = (abc[0] / safety, abc[1] / safety ** 3, 0.0)
+        safe.append(abc)
+    z = np.zeros(T, dtype=bool)
+    return Schedule(np.array(safe), np.array(unsafe), np.array(ells), np.array(us), z,
+                    np.zeros(T, dtype=int))
+
+
 def composite(abc_list, x):
     """phi_T(x) = p_T(...p_1(x)) on scalars/arrays (eq. composition)."""
     y = np.asarray(x, dtype=np.float64)

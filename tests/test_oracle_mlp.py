@@ -39,20 +39,40 @@ def test_features_are_scale_and_rotation_invariant_where_stated():
 
 
 def test_class_errors_match_matrix_iteration():
-    """Appendix C: the label's per-class error equals ||X_T - UV^T||_2 of the iteration."""
+    """Appendix C: the label's per-class error equals ||X_T' - UV^T||_2 of the
+    class's T'-step iteration."""
     r = synth.rng(5)
     G = synth.usv(r, 24, 48, synth.spectrum_loguniform(r, 24, 1e-4, 1.0))
     s_hat = SP.normalised_spectrum(G.sigma)
     errs = M.class_errors(s_hat, 5)
-    for c in (0, 4, 7):
-        abc = S.greedy_schedule(M.CLASS_ELL[c], 5).abc
+    steps = M.class_steps(5)
+    for c in (0, 3, 4, 7):
+        abc = S.greedy_schedule(M.CLASS_ELL[c], int(steps[c])).abc
         X = I.polar_express(G.G, abc)
         assert abs(SP.spec_norm(X - G.polar()) - errs[c]) <= 1e-10
 
 
-def test_label_prefers_larger_ell_on_ties():
-    assert M.label([0.5, 0.5, 0.7]) == 0
-    assert M.label([0.9, 0.3, 0.3]) == 1
+def test_class_table():
+    """Class 4 is the paper's fixed schedule for all T steps; the others pair
+    an l with T' <= T; a class's T'-step schedule is the first T' steps of its
+    T-step schedule (the construction is greedy)."""
+    assert M.CLASS_TABLE[M.FIXED_CLASS] == (1e-3, None)
+    st = M.class_steps(5)
+    assert st[M.FIXED_CLASS] == 5 and np.all(st <= 5) and st.min() >= 1
+    for (l, _), k in zip(M.CLASS_TABLE, st):
+        assert np.array_equal(S.greedy_schedule(l, int(k)).abc, S.greedy_schedule(l, 5).abc[:k])
+    assert np.array_equal(M.class_steps(3), np.minimum(st, 3))
+
+
+def test_label_rule():
+    """Fewest steps within the fixed class's error; then the smaller error."""
+    steps = np.array([2, 3, 3, 4, 5, 4, 5, 5])
+    errs = np.array([0.5, 0.2, 0.1, 0.05, 0.1, 0.03, 0.02, 0.01])
+    assert M.label(errs, steps) == 2          # 3 steps, 0.1 <= 0.1
+    errs2 = errs.copy(); errs2[4] = 0.04
+    assert M.label(errs2, steps) == 5         # 4 steps: class 5 (0.03) beats class 3 (0.05 > 0.04)
+    errs3 = errs.copy(); errs3[4] = 0.015
+    assert M.label(errs3, steps) == 7         # only 5-step classes qualify; the smallest error
 
 
 def test_gradient_matches_finite_differences():
@@ -84,10 +104,14 @@ def test_adam_first_step_and_convergence():
 
 
 def test_learning_signal_exists():
-    """The best class depends on the spectrum: a slowly decaying spectrum prefers
-    a larger l than the fixed 1e-3, a log-uniform one down to 1e-5 a smaller l."""
+    """The best class depends on the spectrum: a slowly decaying spectrum needs
+    fewer steps than the fixed schedule (a class of larger l with T' < T), a
+    log-uniform one down to 1e-5 a smaller l over all T steps."""
     T = 5
+    steps = M.class_steps(T)
     flat = SP.normalised_spectrum(np.linspace(1.0, 0.5, 500))
     wide = SP.normalised_spectrum(np.geomspace(1.0, 1e-5, 500))
-    assert M.label(M.class_errors(flat, T)) < M.FIXED_CLASS
-    assert M.label(M.class_errors(wide, T)) > M.FIXED_CLASS
+    cf = M.label(M.class_errors(flat, T), steps)
+    cw = M.label(M.class_errors(wide, T), steps)
+    assert steps[cf] < T
+    assert steps[cw] == T and M.CLASS_ELL[cw] < 1e-3

@@ -268,3 +268,32 @@ def test_extend_repeats_last():
     ext = S.extend_schedule(tab, 5)
     assert ext.shape == (5, 3)
     assert np.array_equal(ext[1:], np.repeat(tab[1:], 4, axis=0))
+
+
+def test_cubic_closed_form_equioscillates_and_is_minimax():
+    """eq. (deg3_solution): the error of beta p_NS(alpha x) takes the value
+    -E at l and u and +E at the interior extremum 1/alpha, and no odd cubic
+    does better on a fine grid (linear programme)."""
+    for lo, hi in [(1e-3, 1.0), (0.05, 1.0), (0.3, 1.7), (0.9, 1.1)]:
+        a, b, E = S.cubic_closed_form(lo, hi)
+        p = lambda x: a * x + b * x ** 3
+        xm = math.sqrt(-a / (3 * b))
+        assert abs((1 - p(lo)) - E) <= 1e-12 and abs((1 - p(hi)) - E) <= 1e-12
+        assert abs((p(xm) - 1) - E) <= 1e-12
+        grid = np.linspace(lo, hi, 200001)
+        assert np.max(np.abs(1 - p(grid))) <= E * (1 + 1e-9) + 1e-15
+        _, E_lp = _lp_minimax(lo, hi, 3)
+        assert abs(E - E_lp) <= 1e-7 * max(1.0, E_lp) + 2e-8
+
+
+def test_cubic_schedule_theorem1_bound():
+    """Theorem 1 for d = 3: without the safety factor the composite's worst
+    error on [l, 1] is 1 - l_{T+1}, and it converges quadratically once the
+    interval is narrow (the error bound roughly squares each step)."""
+    sch = S.greedy_schedule_cubic(1e-3, 12, safety=1.0)
+    x = np.linspace(1e-3, 1.0, 400001)
+    for T in (4, 8, 12):
+        err = np.max(np.abs(1.0 - S.composite(sch.abc[:T], x)))
+        assert abs(err - (1.0 - sch.ell[T])) <= 1e-9
+    e = 1.0 - sch.ell
+    assert e[12] <= 1e-6 and e[11] <= 10 * e[10] ** 2
