@@ -94,16 +94,38 @@ void pe_coeff_opts_default(pe_coeff_opts* opts);
 pe_status pe_coeffs(double ell, int32_t T, const pe_coeff_opts* opts, double* abc,
                     double* bounds, double* err_bound, int32_t* iters);
 
+/* Degree-3 schedule (Appendix E, eq. deg3_solution; Theorem 1): the greedy
+ * composition of closed-form minimax cubics, safety factor as above (opts'
+ * cushion is ignored).  abc receives T triples (a_t, b_t, 0), usable wherever
+ * a degree-5 schedule is (the online stage skips the A^2 product of a step
+ * whose c_t is 0).  bounds / err_bound as for pe_coeffs.  PE_EINVAL on bad
+ * arguments. */
+pe_status pe_coeffs_cubic(double ell, int32_t T, const pe_coeff_opts* opts, double* abc,
+                          double* bounds, double* err_bound);
+
 /* ---------------------------------------------------------------------------
  * Online stage.
  * ------------------------------------------------------------------------- */
 typedef struct {
   const void* G;       /* device, m x n, leading dimension ldg (elements), dtype g_dtype */
-  void* X;             /* device, m x n output, leading dimension ldx, dtype x_dtype */
+  void* X;             /* device, m x n output, leading dimension ldx, dtype x_dtype;
+                          may be NULL when W is given */
   int64_t m, n;        /* m, n >= 0; m = 0 or n = 0 is a no-op */
   int64_t ldg, ldx;    /* >= n */
   int32_t g_dtype;     /* pe_dtype */
   int32_t x_dtype;     /* pe_dtype */
+  /* Muon step fused around the iteration (Section 1.1, eq. muon), optional:
+   *   M <- beta M + (1 - beta) G   (in place; the iteration then runs on M)
+   *   W <- (1 - lr wd) W - lr X_T  (in place, in the last step's epilogue)
+   * with beta, lr, wd from pe_opts.  M: device FP32, m x n, leading dimension
+   * ldm >= n, or NULL (the iteration runs on G).  W: device, m x n, ldw >= n,
+   * dtype w_dtype, or NULL.  Not with the learned fallback (fallback_tau > 0),
+   * whose re-run would apply the step twice. */
+  float* M;
+  int64_t ldm;
+  void* W;
+  int64_t ldw;
+  int32_t w_dtype;
 } pe_matrix;
 
 typedef struct {
@@ -132,6 +154,30 @@ typedef struct {
    * 1 = never split, n in 2..64 = at most n.  Results agree across settings up
    * to the FP32 summation order.  PE_EINVAL outside 0..64. */
   int32_t split_k;
+  /* Fast rectangular iteration (Appendix G, Algorithm 4): with fast_restart =
+   * k >= 1 the T steps run in segments of k steps, each computing the
+   * composite as Q X with Q a polynomial in the segment's Gram matrix Y (two
+   * products with the long side per segment instead of two per step); the
+   * first segment's Y is Y + fast_eps I (the paper's guard, 1e-3; 0 keeps
+   * the composite of the ordinary iteration exactly).  FP32 compute only
+   * (with bf16 operands the accumulated Q loses the 3e-2 accuracy bar on
+   * general spectra), no learned choice of l; PE_EUNSUPPORTED otherwise.
+   * 0 = the ordinary iteration. */
+  int32_t fast_restart;
+  float fast_eps;
+  /* Muon hyperparameters (used where a pe_matrix carries M or W): momentum
+   * coefficient beta in [0, 1), learning rate lr, decoupled weight decay wd. */
+  float muon_beta;
+  float muon_lr;
+  float muon_wd;
+  /* Spectrum-aware initialisation (appendix on matrices with large spectral
+   * gaps, k = 1): > 0 runs that many power-method steps on the first Gram
+   * matrix A = X_0 X_0^T (from a fixed sign vector) for z <= sigma_1, and when
+   * z > w = sqrt(||X_0||_F^2 - z^2) applies the cubic through (w, 1) and
+   * (z, 1) as an extra first step before the T scheduled ones (per matrix, on
+   * the device).  Not with FP8 steps, the learned choice of l or the fast
+   * iteration (PE_EUNSUPPORTED).  0 = off. */
+  int32_t spectral_init;
 } pe_opts;
 
 #define PE_CLASSES 8
@@ -234,7 +280,8 @@ pe_status pe_mlp_train_step(float* params, float* m, float* v, int32_t step, flo
 int32_t pe_tile_count(void);
 const char* pe_tile_name(int32_t tile_id);
 /* Lines "<shape-class>_<regime> <tile-id>" ('#' starts a comment); tile-id 1
- * or 2; regime x1 (a call with one matrix) or xN (a batch).  With a table
+ * or 2; regime xN for calls of at least 3e12 algorithmic FLOP per step
+ * (sum of 3 s^2 L + s^3), x1 below.  With a table
  * loaded and opts.tile = 0, each matrix of a call takes its class's tile, and
  * every phase of the call launches once per (precision, tile) class present;
  * matrices whose class is missing take the built-in rule (256 for s >= 512 in

@@ -21,7 +21,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["coeffs", "polar", "polar_batched", "polar_noalloc", "Plan", "workspace_size", "lib", "PEError",
+__all__ = ["coeffs", "coeffs_cubic", "split_heads", "load_predictor", "polar", "polar_batched", "polar_noalloc", "muon_step", "Plan", "workspace_size", "lib", "PEError",
            "COMPUTE", "LIB_PATH"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -50,7 +50,9 @@ class CoeffOpts(ctypes.Structure):
 class Matrix(ctypes.Structure):
     _fields_ = [("G", ctypes.c_void_p), ("X", ctypes.c_void_p), ("m", ctypes.c_int64),
                 ("n", ctypes.c_int64), ("ldg", ctypes.c_int64), ("ldx", ctypes.c_int64),
-                ("g_dtype", ctypes.c_int32), ("x_dtype", ctypes.c_int32)]
+                ("g_dtype", ctypes.c_int32), ("x_dtype", ctypes.c_int32),
+                ("M", ctypes.c_void_p), ("ldm", ctypes.c_int64), ("W", ctypes.c_void_p),
+                ("ldw", ctypes.c_int64), ("w_dtype", ctypes.c_int32)]
 
 
 class Opts(ctypes.Structure):
@@ -58,7 +60,10 @@ class Opts(ctypes.Structure):
                 ("compute", ctypes.c_int32), ("fp8_steps", ctypes.c_int32),
                 ("norm_mode", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("predictor", ctypes.c_void_p), ("force_class", ctypes.c_int32),
-                ("fallback_tau", ctypes.c_float), ("split_k", ctypes.c_int32)]
+                ("fallback_tau", ctypes.c_float), ("split_k", ctypes.c_int32),
+                ("fast_restart", ctypes.c_int32), ("fast_eps", ctypes.c_float),
+                ("muon_beta", ctypes.c_float), ("muon_lr", ctypes.c_float), ("muon_wd", ctypes.c_float),
+                ("spectral_init", ctypes.c_int32)]
 
 
 MLP_PARAMS = 5768
@@ -86,6 +91,10 @@ def lib() -> ctypes.CDLL:
         L.pe_coeffs.argtypes = [ctypes.c_double, ctypes.c_int32, ctypes.POINTER(CoeffOpts),
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+        L.pe_coeffs_cubic.restype = ctypes.c_int
+        L.pe_coeffs_cubic.argtypes = [ctypes.c_double, ctypes.c_int32, ctypes.POINTER(CoeffOpts),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]
         L.pe_coeff_opts_default.restype = None
         L.pe_coeff_opts_default.argtypes = [ctypes.POINTER(CoeffOpts)]
         L.pe_workspace_size.restype = ctypes.c_size_t
@@ -146,6 +155,13 @@ def lib() -> ctypes.CDLL:
     return _LIB
 
 
+def _invalid(L, count, mats, o):
+    """pe_workspace_size returned 0: raise with the status the call itself
+    reports (argument checks run before anything touches the device)."""
+    st = L.pe_polar_batched(count, mats, ctypes.byref(o), None, 0, None)
+    _check(st if st not in (0, 4) else 1, "argument check")
+
+
 def _check(st: int, where: str):
     if st != 0:
         detail = lib().pe_last_error().decode() if st in (4, 5) else ""
@@ -184,6 +200,36 @@ def coeffs(ell: float = 1e-3, T: int = 5, cushion: float | None = None, safety: 
     return Coeffs(abc.reshape(T, 3), bounds.reshape(T + 1, 2), err.value, iters)
 
 
+def coeffs_cubic(ell: float = 1e-3, T: int = 8, safety: float | None = None,
+                 safety_on_last: bool = True) -> Coeffs:
+    """Degree-3 greedy schedule (pe_coeffs_cubic, host FP64): (a, b, 0) triples."""
+    L = lib()
+    o = CoeffOpts()
+    L.pe_coeff_opts_default(ctypes.byref(o))
+    if safety is not None:
+        o.safety = safety
+    o.safety_on_last = 1 if safety_on_last else 0
+    abc = np.zeros(3 * T)
+    bounds = np.zeros(2 * (T + 1))
+    err = ctypes.c_double(0.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(L.pe_coeffs_cubic(float(ell), int(T), ctypes.byref(o), abc.ctypes.data_as(dp),
+                             bounds.ctypes.data_as(dp), ctypes.byref(err)), "pe_coeffs_cubic")
+    return Coeffs(abc.reshape(T, 3), bounds.reshape(T + 1, 2), err.value, np.zeros(T, dtype=np.int32))
+
+
+def split_heads(G, heads: int, axis: int = 1):
+    """Views of a weight gradient split into ``heads`` equal slices along
+    ``axis`` (Appendix G, application to Muon: each attention head's block of
+    [W_Q | W_K | W_V] or W_O as its own matrix), for pe_polar_batched: no
+    copies, the views keep G's leading dimension."""
+    size = G.shape[axis]
+    if size % heads:
+        raise ValueError("the split axis must divide into the heads")
+    w = size // heads
+    return [G.narrow(axis, h * w, w) for h in range(heads)]
+
+
 # ------------------------------------------------------------------- online
 def _dtype_code(dt):
     import torch
@@ -194,20 +240,38 @@ def _dtype_code(dt):
     raise TypeError(f"unsupported dtype {dt} (float32 or bfloat16)")
 
 
-def _matrix(G, X) -> Matrix:
-    if G.dim() != 2 or X.dim() != 2 or tuple(G.shape) != tuple(X.shape):
-        raise ValueError("G and X must be 2-D of equal shape")
-    if not G.is_cuda or not X.is_cuda:
-        raise ValueError("G and X must be device tensors")
+def _matrix(G, X, M=None, W=None) -> Matrix:
+    """Descriptor of one matrix: input G, output X (or None when W is given),
+    and the optional Muon momentum M (FP32, updated in place) and weights W."""
+    import torch
+    for name, t in (("G", G), ("X", X), ("M", M), ("W", W)):
+        if t is None:
+            continue
+        if t.dim() != 2 or tuple(t.shape) != tuple(G.shape):
+            raise ValueError(f"{name} must be 2-D of G's shape")
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+        if G.numel() > 0 and t.stride(1) != 1:
+            raise ValueError(f"rows of {name} must be contiguous")
+    if X is None and W is None:
+        raise ValueError("an output X or weights W are needed")
+    if M is not None and M.dtype != torch.float32:
+        raise TypeError("the momentum M must be float32")
     m, n = G.shape
-    if m > 0 and n > 0 and (G.stride(1) != 1 or X.stride(1) != 1):
-        raise ValueError("rows of G and X must be contiguous")
-    return Matrix(G.data_ptr(), X.data_ptr(), m, n, max(G.stride(0), n), max(X.stride(0), n),
-                  _dtype_code(G.dtype), _dtype_code(X.dtype))
+
+    def ld(t):
+        return max(t.stride(0), n) if t is not None else 0
+
+    return Matrix(G.data_ptr(), X.data_ptr() if X is not None else None, m, n, ld(G), ld(X),
+                  _dtype_code(G.dtype), _dtype_code(X.dtype) if X is not None else 0,
+                  M.data_ptr() if M is not None else None, ld(M),
+                  W.data_ptr() if W is not None else None, ld(W),
+                  _dtype_code(W.dtype) if W is not None else 0)
 
 
 def _opts(T, abc, compute, fp8_steps, norm_mode, tile, predictor=None, force_class=-1,
-          fallback_tau=0.0, split_k=0):
+          fallback_tau=0.0, split_k=0, fast_restart=0, fast_eps=1e-3, muon=(0.0, 0.0, 0.0),
+          spectral_init=0):
     abc = np.ascontiguousarray(np.asarray(abc, dtype=np.float64).reshape(-1))
     if abc.size != 3 * T:
         raise ValueError("abc must hold 3*T coefficients")
@@ -218,7 +282,8 @@ def _opts(T, abc, compute, fp8_steps, norm_mode, tile, predictor=None, force_cla
         pred = predictor.data_ptr()
     o = Opts(int(T), abc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), COMPUTE[compute],
              int(fp8_steps), int(norm_mode), int(tile), pred, int(force_class), float(fallback_tau),
-             int(split_k))
+             int(split_k), int(fast_restart), float(fast_eps), float(muon[0]), float(muon[1]),
+             float(muon[2]), int(spectral_init))
     return o, abc
 
 
@@ -287,6 +352,22 @@ def mlp_grad(params, feats, labels, stream=None):
     return loss, grad
 
 
+def load_predictor(path=None, T: int = 5, device="cuda"):
+    """The committed l-predictor (weights trained by train_predictor on the
+    device kernels) as a device tensor, and its metadata."""
+    import json
+    import torch
+    base = path or os.path.join(HERE, f"predictor_T{T}")
+    theta = np.load(base + ".npy", allow_pickle=False)
+    with open(base + ".json") as f:
+        meta = json.load(f)
+    if theta.shape != (MLP_PARAMS,) or theta.dtype != np.float32:
+        raise ValueError("predictor file does not hold MLP_PARAMS float32 values")
+    if meta.get("T") != T:
+        raise ValueError(f"predictor trained for T={meta.get('T')}, asked for T={T}")
+    return torch.from_numpy(theta).to(device), meta
+
+
 class MLPTrainer:
     """Adam on the device: params, moments and the per-step workspace stay resident."""
 
@@ -315,32 +396,43 @@ class MLPTrainer:
 
 def polar(G, T: int = 5, ell: float = 1e-3, abc=None, compute: str = "bf16", out=None,
           out_dtype=None, fp8_steps: int = 0, norm_mode: int = 0, tile: int = 0, stream=None,
-          predictor=None, force_class: int = -1, fallback_tau: float = 0.0, split_k: int = 0):
+          predictor=None, force_class: int = -1, fallback_tau: float = 0.0, split_k: int = 0,
+          fast_restart: int = 0, fast_eps: float = 1e-3, spectral_init: int = 0):
     """X_T for one matrix (pe_polar).  Returns a new tensor unless ``out`` is given."""
     return polar_batched([G], T, ell, abc, compute, [out] if out is not None else None,
                          out_dtype, fp8_steps, norm_mode, tile, stream, predictor, force_class,
-                         fallback_tau, split_k=split_k, _single=True)[0]
+                         fallback_tau, split_k=split_k, fast_restart=fast_restart,
+                         fast_eps=fast_eps, spectral_init=spectral_init, _single=True)[0]
 
 
 def polar_batched(Gs, T: int = 5, ell: float = 1e-3, abc=None, compute: str = "bf16", outs=None,
                   out_dtype=None, fp8_steps: int = 0, norm_mode: int = 0, tile: int = 0,
                   stream=None, predictor=None, force_class: int = -1, fallback_tau: float = 0.0,
-                  split_k: int = 0, _single: bool = False):
-    """X_T for a list of matrices of any shapes (pe_polar_batched)."""
+                  split_k: int = 0, fast_restart: int = 0, fast_eps: float = 1e-3,
+                  moms=None, weights=None, muon=(0.0, 0.0, 0.0), spectral_init: int = 0,
+                  _single: bool = False):
+    """X_T for a list of matrices of any shapes (pe_polar_batched).  With
+    ``moms`` / ``weights`` (lists of device tensors, entries may be None) the
+    Muon step is fused in: M <- beta M + (1-beta) G before the iteration and
+    W <- (1 - lr wd) W - lr X_T after it, muon = (beta, lr, wd); ``outs`` may
+    then hold None entries (no X written)."""
     import torch
     Gs = list(Gs)
+    n = len(Gs)
+    moms = list(moms) if moms is not None else [None] * n
+    weights = list(weights) if weights is not None else [None] * n
     if outs is None:
         outs = [torch.empty(G.shape, dtype=out_dtype or G.dtype, device=G.device) for G in Gs]
     sched = _schedule(T, ell, abc)
     o, _keep = _opts(T, sched, compute, fp8_steps, norm_mode, tile, predictor, force_class,
-                     fallback_tau, split_k)
-    mats = (Matrix * max(1, len(Gs)))()
-    for i, (G, X) in enumerate(zip(Gs, outs)):
-        mats[i] = _matrix(G, X)
+                     fallback_tau, split_k, fast_restart, fast_eps, muon, spectral_init)
+    mats = (Matrix * max(1, n))()
+    for i, (G, X, M, W) in enumerate(zip(Gs, outs, moms, weights)):
+        mats[i] = _matrix(G, X, M, W)
     L = lib()
     nbytes = int(L.pe_workspace_size(len(Gs), mats, ctypes.byref(o)))
     if nbytes == 0 and len(Gs) > 0:
-        _check(1, "pe_workspace_size")
+        _invalid(L, len(Gs), mats, o)
     dev = Gs[0].device if Gs else None
     ws_buf, ws = _workspace(nbytes, dev) if Gs else (None, 0)
     st = _stream(stream)
@@ -374,6 +466,18 @@ def polar_noalloc(G, out, T: int = 5, ell: float = 1e-3, abc=None, compute: str 
     return out
 
 
+def muon_step(Gs, moms, weights, lr: float, beta: float = 0.9, wd: float = 0.0, T: int = 5,
+              ell: float = 1e-3, abc=None, compute: str = "bf16", outs=None, **kw):
+    """One Muon optimizer step over a list of weight matrices (Section 1.1):
+    M <- beta M + (1 - beta) G, W <- (1 - lr wd) W - lr polar(M), with
+    polar(M) from Polar Express, all in grouped launches (pe_polar_batched).
+    Updates ``moms`` (FP32) and ``weights`` in place; returns ``outs`` (None
+    entries unless given)."""
+    outs = list(outs) if outs is not None else [None] * len(list(Gs))
+    return polar_batched(Gs, T, ell, abc, compute, outs, moms=moms, weights=weights,
+                         muon=(beta, lr, wd), **kw)
+
+
 def quantize_e4m3(x, scale: float, stream=None):
     """e4m3 bytes of x * scale with the FP8 path's device conversion."""
     import torch
@@ -391,23 +495,28 @@ class Plan:
     def __init__(self, Gs, outs=None, T: int = 5, ell: float = 1e-3, abc=None, compute: str = "bf16",
                  out_dtype=None, fp8_steps: int = 0, norm_mode: int = 0, tile: int = 0, stream=None,
                  predictor=None, force_class: int = -1, fallback_tau: float = 0.0,
-                 ws_fill=None, split_k: int = 0):
+                 ws_fill=None, split_k: int = 0, fast_restart: int = 0, fast_eps: float = 1e-3,
+                 moms=None, weights=None, muon=(0.0, 0.0, 0.0), spectral_init: int = 0):
         import torch
         self.Gs = list(Gs)
+        n = len(self.Gs)
+        self.moms = list(moms) if moms is not None else [None] * n
+        self.weights = list(weights) if weights is not None else [None] * n
         self.outs = outs if outs is not None else [
             torch.empty(G.shape, dtype=out_dtype or G.dtype, device=G.device) for G in self.Gs]
         self.T = T
         self.abc = _schedule(T, ell, abc)
         self._predictor = predictor
         o, self._abc_keep = _opts(T, self.abc, compute, fp8_steps, norm_mode, tile, predictor,
-                                  force_class, fallback_tau, split_k)
-        self._mats = (Matrix * max(1, len(self.Gs)))()
-        for i, (G, X) in enumerate(zip(self.Gs, self.outs)):
-            self._mats[i] = _matrix(G, X)
+                                  force_class, fallback_tau, split_k, fast_restart, fast_eps, muon,
+                                  spectral_init)
+        self._mats = (Matrix * max(1, n))()
+        for i, (G, X, M, W) in enumerate(zip(self.Gs, self.outs, self.moms, self.weights)):
+            self._mats[i] = _matrix(G, X, M, W)
         L = lib()
         self.ws_bytes = int(L.pe_workspace_size(len(self.Gs), self._mats, ctypes.byref(o)))
         if self.ws_bytes == 0:
-            _check(1, "pe_workspace_size")
+            _invalid(L, len(self.Gs), self._mats, o)
         self._ws_buf, self._ws = _workspace(self.ws_bytes, self.Gs[0].device)
         if ws_fill is not None:
             # the library must not depend on the workspace's prior contents

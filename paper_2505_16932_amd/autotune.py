@@ -1,8 +1,9 @@
 """Autotuner of the block tile per shape class and call regime.
 
 For each shape class (precision, s bucket, aspect bucket) and regime -- "x1",
-a call with one matrix, and "xN", a batch large enough to keep the device busy
-for tens of milliseconds per step -- it builds a batch of that class, times
+a call with one matrix (below the library's 3e12 FLOP-per-step batch
+threshold), and "xN", a batch of ~1.5e13 FLOP per step -- it builds a batch
+of that class, times
 whole plan launches (hipGraph replays, HIP events on the launch stream) with
 each compiled tile (1 = 128 x 128, 2 = 256 x 256), and writes
 "<shape-class>_<regime> <tile-id>" lines to a table that pe_tile_table_load()

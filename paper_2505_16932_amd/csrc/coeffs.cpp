@@ -203,3 +203,41 @@ extern "C" pe_status pe_coeffs(double ell, int32_t T, const pe_coeff_opts* opts,
   }
   return PE_OK;
 }
+
+// Degree-3 schedule: the greedy composition (Theorem 1) of the closed-form
+// minimax cubics of eq. (deg3_solution), p(x) = beta p_NS(alpha x) with
+// p_NS(x) = (3x - x^3)/2, alpha = sqrt(3 / (u^2 + l u + l^2)) and
+// beta = 4 / (2 + l u (l + u) alpha^3); the error equioscillates at l, 1/alpha
+// and u with E = beta - 1, so l_{t+1} = 1 - E and u_{t+1} = 1 + E.  The safety
+// factor as for degree 5; no cushion.  abc receives (a_t, b_t, 0) triples.
+extern "C" pe_status pe_coeffs_cubic(double ell, int32_t T, const pe_coeff_opts* opts, double* abc,
+                                     double* bounds, double* err_bound) {
+  pe_coeff_opts o;
+  pe_coeff_opts_default(&o);
+  if (opts) o = *opts;
+  if (!abc || !(ell > 0.0) || !(ell < 1.0) || T < 1 || T > 64) return PE_EINVAL;
+  if (!(o.safety >= 1.0)) return PE_EINVAL;
+  double l = ell, u = 1.0;
+  if (bounds) {
+    bounds[0] = l;
+    bounds[1] = u;
+  }
+  for (int t = 0; t < T; ++t) {
+    const double alpha = std::sqrt(3.0 / (u * u + l * u + l * l));
+    const double beta = 4.0 / (2.0 + l * u * (l + u) * alpha * alpha * alpha);
+    const double a = 1.5 * beta * alpha, b = -0.5 * beta * alpha * alpha * alpha;
+    l = l * (a + b * l * l);
+    u = 2.0 - l;
+    const bool safe = o.safety != 1.0 && (o.safety_on_last || t < T - 1);
+    const double s = safe ? o.safety : 1.0;
+    abc[3 * t + 0] = a / s;
+    abc[3 * t + 1] = b / (s * s * s);
+    abc[3 * t + 2] = 0.0;
+    if (bounds) {
+      bounds[2 * (t + 1) + 0] = l;
+      bounds[2 * (t + 1) + 1] = u;
+    }
+  }
+  if (err_bound) *err_bound = 1.0 - l;
+  return PE_OK;
+}

@@ -41,6 +41,9 @@ enum : int32_t {
   kScAmaxG = 1,    // max |G| (float bits)
   kScFro = 2,      // ||G||_F as float
   kScBeta = 3,     // shift beta_t = tr(B_t)/s of the current step (update: a + beta)
+  kScPowN = 4,     // spectrum-aware init: ||A v|| of the last power step
+  kScInitA = 5,    // spectrum-aware init: coefficients (a, b) of the init cubic
+  kScInitB = 6,
   kScAmaxX = 8,    // +t : max |X_t| (uint bits of a non-negative float), t = 0..63
   kScAmaxA = 72,   // +t : max |A_t| for step t (0-based)
   kScN = 136
@@ -79,7 +82,19 @@ struct MatDesc {
   // FP8 steps on the 256 tile: e4m3 copies of the Gram-side operands
   uint8_t* Xq;      // sp x Lp: e4m3(q X_t), written by the quantisation pass
   uint8_t* Aq;      // sp x sp: e4m3(q A_t)
+  // fast rectangular iteration (FP32): sp x sp buffers, see kFb* below
+  float* fb[6];
+  // Muon step (caller's m x n layout): momentum M (FP32) updated by the norm
+  // pass, weights W updated by the last step's epilogue
+  float* M;
+  void* W;
+  int64_t ldm, ldw;
+  int32_t w_bf16, pad_;
 };
+
+// Roles of MatDesc::fb in the fast rectangular iteration: the segment's R_t
+// (ping-pong), D_t = Q_t - (prod a) I (ping-pong), P = R_t B_t, and B_t.
+enum : int32_t { kFbR0 = 0, kFbR1 = 1, kFbD0 = 2, kFbP = 3, kFbB = 4, kFbD1 = 5, kFbNone = -1 };
 
 struct KArgs {
   const MatDesc* descs;  // device array of `count` descriptors
@@ -102,6 +117,16 @@ struct KArgs {
   float tau;             // fallback threshold
   int32_t est_phase;     // power-iteration phase selector
   const int32_t* ord;    // position -> matrix of this phase's item order (nullptr: identity)
+  // fast rectangular iteration (gemm_fast_kernel and the update): operand and
+  // epilogue buffers (MatDesc::fb roles) and coefficients of
+  //   out = cacc * acc + c1 * E1 + c2 * E2 + cdiag * I
+  int32_t fast;          // 1: a launch of the fast iteration
+  int32_t fp_, fq_, fe1, fe2, fout;
+  float cacc, c1, c2, cdiag;
+  int32_t fscale;        // cacc is multiplied by sigma^2 (first segment's Gram)
+  float mbeta, mlr, mwd; // Muon momentum coefficient, learning rate, weight decay
+  int32_t init_step;     // the spectrum-aware init step: (a, b, 0) from scal[kScInitA/B]
+  const int32_t* sel_steps;  // [n_sched]: steps T' of each class's schedule (learned path)
 };
 
 // Spectral shift of the update.  In real arithmetic

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -26,6 +27,8 @@ hipError_t launch_finalize(const KArgs& a, hipStream_t st);
 hipError_t launch_select(const KArgs& a, hipStream_t st);
 hipError_t launch_combine(int prec, const KArgs& a, hipStream_t st);
 hipError_t launch_quant(int kind, const KArgs& a, int grid_cap, hipStream_t st);
+hipError_t launch_fast(int kind, const KArgs& a, int grid_cap, hipStream_t st);
+hipError_t launch_power(int prec, int phase, const KArgs& a, hipStream_t st);
 hipError_t launch_est(const KArgs& a, int iters, hipStream_t st, const int32_t* offs_a, int total_a,
                       const int32_t* offs_b, int total_b);
 hipError_t launch_mlp_forward(const float* params, const float* feats, int B, float* logits,
@@ -48,10 +51,16 @@ namespace {
 thread_local std::string g_last_error;
 
 enum Phase { PH_PREP = 0, PH_GRAM, PH_A2, PH_UPD, PH_RGRAM, PH_RA2, PH_COMBINE, PH_EST_A, PH_EST_B,
-             PH_QX, PH_QA, PH_N };
+             PH_QX, PH_QA, PH_FSYRK, PH_PW, PH_N };
 
-constexpr double kClassEll[kClasses] = {1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5};
+// Schedule classes of the learned path: (l, T'), T' = 0 meaning the call's T;
+// class 4 is the caller's schedule for all T steps.  Steps past a class's T'
+// leave the matrix as it is (its kernels skip it; the last step copies X).
+struct ClassDef { double ell; int steps; };
+constexpr ClassDef kClassTable[kClasses] = {{1e-1, 2}, {1e-1, 3}, {3e-2, 3}, {1e-2, 4},
+                                            {1e-3, 0}, {3e-3, 4}, {3e-4, 0}, {1e-4, 0}};
 constexpr int kFixedClass = 4;
+int class_steps(int c, int T) { return kClassTable[c].steps > 0 ? std::min(T, kClassTable[c].steps) : T; }
 constexpr int kEstIters = 8;
 
 bool learned_mode(const pe_opts* o) { return o->predictor != nullptr || o->force_class >= 0; }
@@ -103,10 +112,12 @@ struct Layout {
 bool valid_matrix(const pe_matrix& m) {
   if (m.m < 0 || m.n < 0) return false;
   if (m.m == 0 || m.n == 0) return true;
-  if (!m.G || !m.X) return false;
-  if (m.ldg < m.n || m.ldx < m.n) return false;
+  if (!m.G || (!m.X && !m.W)) return false;
+  if (m.ldg < m.n || (m.X && m.ldx < m.n)) return false;
   if (m.g_dtype != PE_F32 && m.g_dtype != PE_BF16) return false;
-  if (m.x_dtype != PE_F32 && m.x_dtype != PE_BF16) return false;
+  if (m.X && m.x_dtype != PE_F32 && m.x_dtype != PE_BF16) return false;
+  if (m.M && m.ldm < m.n) return false;
+  if (m.W && (m.ldw < m.n || (m.w_dtype != PE_F32 && m.w_dtype != PE_BF16))) return false;
   if (m.m > (1 << 20) || m.n > (1 << 20)) return false;
   return true;
 }
@@ -124,6 +135,15 @@ pe_status check_opts(const pe_opts* o) {
   if (o->force_class < -1 || o->force_class >= kClasses) return PE_EINVAL;
   if (!std::isfinite(o->fallback_tau)) return PE_EINVAL;
   if (o->split_k < 0 || o->split_k > 64) return PE_EINVAL;
+  if (o->fast_restart < 0 || !std::isfinite(o->fast_eps) || o->fast_eps < 0.0f) return PE_EINVAL;
+  if (o->fast_restart > 0 &&
+      (o->compute != PE_COMPUTE_F32 || learned_mode(o) || o->tile == 2)) return PE_EUNSUPPORTED;
+  if (!(o->muon_beta >= 0.0f && o->muon_beta < 1.0f) || !std::isfinite(o->muon_lr) ||
+      !std::isfinite(o->muon_wd)) return PE_EINVAL;
+  if (o->spectral_init < 0 || o->spectral_init > 1000) return PE_EINVAL;
+  if (o->spectral_init > 0 &&
+      ((o->compute == PE_COMPUTE_FP8 && o->fp8_steps > 0) || learned_mode(o) || o->fast_restart > 0))
+    return PE_EUNSUPPORTED;
   return PE_OK;
 }
 
@@ -159,18 +179,24 @@ int prec_for(const pe_opts* o, int64_t s) {
   return kBF16;
 }
 
+// Call regimes of the autotuned table: "xN" for calls with at least
+// kBatchFlops algorithmic FLOP per step (3 s^2 L + s^3 summed over the
+// matrices; the autotuner's batches carry ~1.5e13), "x1" below (its single
+// matrices carry at most ~1.3e12).
+constexpr double kBatchFlops = 3e12;
+
 // Block tile of one matrix.  Forced by opts.tile; else the autotuned table's
-// entry for the matrix's shape class in the call's regime ("x1": a call with
-// one matrix, "xN": a batch); else 256 for bf16 matrices with s >= 512 in
-// calls whose update has at least one 256-tile per CU, 128 otherwise.
-int tile_for(const pe_opts* o, int prec, int64_t s, int64_t L, int count, int64_t upd_tiles256) {
+// entry for the matrix's shape class in the call's regime; else 256 for bf16
+// matrices with s >= 512 in calls whose update has at least one 256-tile per
+// CU, 128 otherwise.
+int tile_for(const pe_opts* o, int prec, int64_t s, int64_t L, bool batch_regime, int64_t upd_tiles256) {
   if (o->tile == 1) return kTileSmall;
   if (o->tile == 2) return kTileLarge;
   if (prec == kF32) return kTileSmall;
   {
     std::lock_guard<std::mutex> lk(g_tab_mu);
     if (!g_tile_table.empty()) {
-      auto it = g_tile_table.find(shape_class(prec, s, L) + (count == 1 ? "_x1" : "_xN"));
+      auto it = g_tile_table.find(shape_class(prec, s, L) + (batch_regime ? "_xN" : "_x1"));
       if (it != g_tile_table.end()) return it->second == 2 ? kTileLarge : kTileSmall;
     }
   }
@@ -187,12 +213,15 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
     for (int c = 0; c < kNCls; ++c) L->offs[p][c].assign(1, 0);
   // update tiles of the whole call at the 256 tile (the built-in tile rule)
   int64_t upd256 = 0;
+  double call_flops = 0.0;
   for (int i = 0; i < count; ++i) {
     const pe_matrix& m = mats[i];
     if (m.m <= 0 || m.n <= 0) continue;
     const int64_t s = std::min(m.m, m.n), Lx = std::max(m.m, m.n);
     upd256 += round_up(s, kTileLarge) / kTileLarge * (round_up(Lx, kTileLarge) / kTileLarge);
+    call_flops += 3.0 * (double)s * s * Lx + (double)s * s * s;
   }
+  const bool batch_regime = call_flops >= kBatchFlops;
   // first pass: precision, tile, shapes and Gram-side tile counts per class
   // (for the split-K choice)
   struct Shape { int64_t s, L, sp, Lp; int nb, nbL, syrk, upd, prep, prec, bt, cls; };
@@ -207,7 +236,7 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
       q.s = std::min(m.m, m.n);
       q.L = std::max(m.m, m.n);
       q.prec = prec_for(o, q.s);
-      q.bt = tile_for(o, q.prec, q.s, q.L, count, upd256);
+      q.bt = tile_for(o, q.prec, q.s, q.L, batch_regime, upd256);
       const int bt = q.bt;
       q.sp = round_up(q.s, bt);
       q.Lp = round_up(q.L, bt);
@@ -234,7 +263,7 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
   off = align_up(off + sizeof(int32_t) * ((size_t)PH_N * kNCls * (count + 1) + (size_t)kNCls * count));
   const bool learned = learned_mode(o);
   L->coef_off = off;
-  if (learned) off = align_up(off + sizeof(float) * kClasses * 3 * (size_t)o->T);
+  if (learned) off = align_up(off + sizeof(float) * kClasses * 3 * (size_t)o->T + sizeof(int32_t) * kClasses);
   for (int i = 0; i < count; ++i) {
     const pe_matrix& m = mats[i];
     const Shape& q = sh[i];
@@ -247,6 +276,11 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
     d.Out = m.X;
     d.ldg = m.ldg;
     d.ldo = m.ldx;
+    d.M = m.M;
+    d.ldm = m.ldm;
+    d.W = m.W;
+    d.ldw = m.ldw;
+    d.w_bf16 = m.W && m.w_dtype == PE_BF16;
     d.m = (int32_t)m.m;
     d.n = (int32_t)m.n;
     d.s = (int32_t)q.s;
@@ -261,7 +295,7 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
       const int64_t per16 = d.g_bf16 ? 8 : 4;
       d.g_vec = ((uintptr_t)m.G % 16 == 0) && (m.ldg % per16 == 0);
     }
-    d.out_bf16 = m.x_dtype == PE_BF16;
+    d.out_bf16 = m.X && m.x_dtype == PE_BF16;
     d.o_vec = d.out_bf16 && ((uintptr_t)m.X % 16 == 0) && (m.ldx % 8 == 0);
     d.nb = q.nb;
     d.nbL = q.nbL;
@@ -289,7 +323,8 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
       d.XT1 = take(X * esz);
       // A in FP32 on the fp32 path; the bf16 paths keep only its bf16 copy,
       // which both A^2 and the bA term of the combine read
-      d.Af = prec == kF32 ? (float*)take(A * 4) : nullptr;
+      // (bf16 paths: an FP32 A only for the spectrum-aware init's power method)
+      d.Af = (prec == kF32 || o->spectral_init > 0) ? (float*)take(A * 4) : nullptr;
       d.As = prec == kF32 ? (void*)d.Af : take(A * 2);
       d.Bs = take(A * esz);
       const int split = std::max(d.gram_split, d.a2_split);
@@ -303,6 +338,9 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
         d.Xq = (uint8_t*)take(X);
         d.Aq = (uint8_t*)take(A);
       }
+      if (o->fast_restart > 0)
+        for (int k = 0; k < 6; ++k) d.fb[k] = (float*)take(A * 4);
+      if (o->spectral_init > 0 && !learned) d.vec = (float*)take(((size_t)2 * q.sp + q.Lp) * 4);
       if (learned) {
         int32_t* ints = (int32_t*)take(64);
         d.selp = ints;
@@ -326,6 +364,10 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
     push(PH_GRAM, q.syrk ? q.syrk * d.gram_split : 0);
     push(PH_A2, q.syrk ? q.syrk * d.a2_split : 0);
     push(PH_UPD, q.syrk ? q.upd : 0);
+    // spectrum-aware init: power-method rows, four per item
+    push(PH_PW, (q.syrk && o->spectral_init > 0) ? (int)((q.sp + 3) / 4) : 0);
+    // fast rectangular iteration: unsplit upper-triangle tiles
+    push(PH_FSYRK, (q.syrk && o->fast_restart > 0) ? q.syrk : 0);
     push(PH_RGRAM, (q.syrk && d.gram_split > 1) ? q.syrk : 0);
     push(PH_RA2, (q.syrk && d.a2_split > 1) ? q.syrk : 0);
     push(PH_COMBINE, (q.syrk && learned) ? (int)q.sp : 0);
@@ -373,8 +415,14 @@ pe_status validate(int count, const pe_matrix* mats, const pe_opts* o) {
   if (count > 100000) return PE_EINVAL;
   pe_status st = check_opts(o);
   if (st != PE_OK) return st;
-  for (int i = 0; i < count; ++i)
+  bool muon = false;
+  for (int i = 0; i < count; ++i) {
     if (!valid_matrix(mats[i])) return PE_EINVAL;
+    muon = muon || mats[i].M || mats[i].W;
+  }
+  // the fallback re-run would apply the momentum and the weight step twice,
+  // and its estimate reads X
+  if (muon && learned_mode(o) && o->fallback_tau > 0.0f) return PE_EUNSUPPORTED;
   return PE_OK;
 }
 
@@ -406,12 +454,18 @@ struct pe_plan {
   int fp8_steps = 0;   // leading steps whose Gram-side products take e4m3 operands
   int T = 0;
   int norm_mode = 0;
+  float muon_beta = 0.0f, muon_lr = 0.0f, muon_wd = 0.0f;
+  int spectral_init = 0;    // > 0: power steps of the spectrum-aware init step
+  int t0 = 0;               // kernel steps before the schedule (1 with the init step)
+  int fast_restart = 0;     // > 0: Algorithm 4 in segments of this many steps
+  float fast_eps = 0.0f;
   std::vector<float> abc;
   bool learned = false;
   const float* mlp = nullptr;
   int force_class = -1;
   float tau = 0.0f;
   float* d_coef = nullptr;     // [classes][T][3]
+  int32_t* d_steps = nullptr;  // [classes]: T' of each class
   Layout L;
   MatDesc* d_descs = nullptr;
   int32_t* d_offs = nullptr;
@@ -433,19 +487,29 @@ pe_status upload(pe_plan* p, char* ws, hipStream_t st) {
   for (int c = 0; c < kNCls; ++c) offs.insert(offs.end(), p->L.ord_gram[c].begin(), p->L.ord_gram[c].end());
   s = put_words(p->d_offs, offs.data(), offs.size() * 4, st);
   if (s != PE_OK || !p->learned) return s;
-  // schedule table of the classes: class 4 is the caller's schedule
-  std::vector<float> tab((size_t)kClasses * p->T * 3);
+  // schedule table of the classes (class 4 is the caller's schedule), rows
+  // past a class's T' the identity step (1, 0, 0); then the classes' T'
+  const size_t nt = (size_t)kClasses * p->T * 3;
+  std::vector<uint32_t> tab(nt + kClasses);
+  float* ft = (float*)tab.data();
   std::vector<double> abc(3 * (size_t)p->T);
   for (int c = 0; c < kClasses; ++c) {
-    if (c == kFixedClass) {
-      for (int i = 0; i < 3 * p->T; ++i) tab[(size_t)c * 3 * p->T + i] = p->abc[i];
-      continue;
+    const int steps = class_steps(c, p->T);
+    if (c != kFixedClass) {
+      // the first T' steps of the greedy T-step schedule are its T'-step schedule
+      s = pe_coeffs(kClassTable[c].ell, p->T, nullptr, abc.data(), nullptr, nullptr, nullptr);
+      if (s != PE_OK) return s;
     }
-    s = pe_coeffs(kClassEll[c], p->T, nullptr, abc.data(), nullptr, nullptr, nullptr);
-    if (s != PE_OK) return s;
-    for (int i = 0; i < 3 * p->T; ++i) tab[(size_t)c * 3 * p->T + i] = (float)abc[i];
+    for (int t = 0; t < p->T; ++t)
+      for (int k = 0; k < 3; ++k) {
+        const float v = t >= steps ? (k == 0 ? 1.0f : 0.0f)
+                                   : (c == kFixedClass ? p->abc[3 * t + k] : (float)abc[3 * t + k]);
+        ft[((size_t)c * p->T + t) * 3 + k] = v;
+      }
+    ((int32_t*)tab.data())[nt + c] = steps;
   }
   p->d_coef = (float*)(ws + p->L.coef_off);
+  p->d_steps = (int32_t*)(p->d_coef + nt);
   return put_words(p->d_coef, tab.data(), tab.size() * 4, st);
 }
 
@@ -456,8 +520,12 @@ KArgs base_args(const pe_plan* p) {
   a.count = p->count;
   a.norm_mode = p->norm_mode;
   a.tmax = p->T;
+  a.mbeta = p->muon_beta;
+  a.mlr = p->muon_lr;
+  a.mwd = p->muon_wd;
   if (p->learned) {
     a.sel_coef = p->d_coef;
+    a.sel_steps = p->d_steps;
     a.mlp = p->mlp;
     a.force_class = p->force_class;
     a.fixed_class = kFixedClass;
@@ -476,12 +544,18 @@ void set_phase(const pe_plan* p, KArgs* a, int ph, int c) {
   a->total = p->L.totals[ph][c];
 }
 
+// kernel step t: the init step (t < t0) or schedule step t - t0
 void set_step(const pe_plan* p, KArgs* a, int t) {
   a->t = t;
-  a->last = t == p->T - 1;
-  a->a = p->abc[3 * t + 0];
-  a->b = p->abc[3 * t + 1];
-  a->c = p->abc[3 * t + 2];
+  a->last = t == p->T + p->t0 - 1;
+  if (t < p->t0) {
+    a->init_step = 1;
+    a->a = a->b = a->c = 0.0f;  // (a, b) per matrix from the power bound; c = 0
+    return;
+  }
+  a->a = p->abc[3 * (t - p->t0) + 0];
+  a->b = p->abc[3 * (t - p->t0) + 1];
+  a->c = p->abc[3 * (t - p->t0) + 2];
 }
 
 pe_status enqueue_norm(const pe_plan* p, hipStream_t st, int fallback = 0) {
@@ -550,11 +624,99 @@ pe_status enqueue_select(const pe_plan* p, hipStream_t st) {
   return PE_OK;
 }
 
+// Algorithm 4 in segments of fast_restart steps (FP32 class only): per
+// segment the Gram matrix, then per step B_t, D_t and (but for the last step)
+// R_{t+1}, and the update X <- q X + D X; see gemm_fast_kernel.
+pe_status enqueue_fast(const pe_plan* p, hipStream_t st) {
+  pe_status s = enqueue_norm(p, st, 0);
+  if (s != PE_OK) return s;
+  const int c = cls_of(kF32, kTileSmall);
+  hipError_t e;
+  // kind 0: Gram of X, 1: symmetric product of two fb buffers
+  auto product = [&](int kind, int fp_, int fq_, int fe1, float c1, int fe2, float c2, float cacc,
+                     int fout, float cdiag, int fscale, int seg) -> pe_status {
+    KArgs a = base_args(p);
+    set_phase(p, &a, PH_FSYRK, c);
+    a.t = seg;
+    a.fast = 1;
+    a.fp_ = fp_;
+    a.fq_ = fq_;
+    a.fe1 = fe1;
+    a.fe2 = fe2;
+    a.c1 = c1;
+    a.c2 = c2;
+    a.cacc = cacc;
+    a.fout = fout;
+    a.cdiag = cdiag;
+    a.fscale = fscale;
+    if ((e = launch_fast(kind, a, kGemmGridCap, st)) != hipSuccess) return hip_fail(e, "fast product");
+    return PE_OK;
+  };
+  int seg = 0;
+  for (int t0 = 0; t0 < p->T; t0 += p->fast_restart, ++seg) {
+    const int k = std::min(p->fast_restart, p->T - t0);
+    int r = kFbR0, dcur = kFbD0;
+    // Y = X X^T (sigma^2 G G^T in the first segment, plus eps I)
+    if ((s = product(0, -1, -1, kFbNone, 0.f, kFbNone, 0.f, 1.f, r, seg == 0 ? p->fast_eps : 0.f,
+                     seg == 0, seg)) != PE_OK) return s;
+    float q = 1.0f;
+    for (int j = 0; j < k; ++j) {
+      const float a = p->abc[3 * (t0 + j)], b = p->abc[3 * (t0 + j) + 1], cc = p->abc[3 * (t0 + j) + 2];
+      // B_t = b R + c R^2 (into D directly on the segment's first step, D_1 = B_1)
+      const int bdst = j == 0 ? dcur : kFbB;
+      if ((s = product(1, r, r, r, b, kFbNone, 0.f, cc, bdst, 0.f, 0, seg)) != PE_OK) return s;
+      if (j > 0) {
+        const int dn = dcur == kFbD0 ? kFbD1 : kFbD0;
+        if ((s = product(1, dcur, kFbB, dcur, a, kFbB, q, 1.f, dn, 0.f, 0, seg)) != PE_OK) return s;
+        dcur = dn;
+      }
+      if (j + 1 < k) {
+        const int rn = r == kFbR0 ? kFbR1 : kFbR0;
+        if ((s = product(1, r, bdst, kFbNone, 0.f, kFbNone, 0.f, 1.f, kFbP, 0.f, 0, seg)) != PE_OK) return s;
+        if ((s = product(1, kFbP, bdst, r, a * a, kFbP, 2.f * a, 1.f, rn, 0.f, 0, seg)) != PE_OK) return s;
+        r = rn;
+      }
+      q *= a;
+    }
+    // X <- q X + D X
+    KArgs u = base_args(p);
+    set_phase(p, &u, PH_UPD, c);
+    u.t = seg;
+    u.last = t0 + k >= p->T;
+    u.a = q;
+    u.b = u.c = 0.0f;
+    u.fast = 1;
+    u.fp_ = dcur;
+    if ((e = launch_gemm(kF32, kTileSmall, 2, u, kGemmGridCap, st)) != hipSuccess)
+      return hip_fail(e, "fast update");
+  }
+  return PE_OK;
+}
+
+// power method on each matrix's step-1 Gram matrix and the init coefficients
+pe_status enqueue_power(const pe_plan* p, hipStream_t st) {
+  KArgs a = base_args(p);
+  hipError_t e;
+  if ((e = launch_power(kF32, 0, a, st)) != hipSuccess) return hip_fail(e, "power init");
+  for (int it = 0; it < p->spectral_init; ++it) {
+    for (int c = 0; c < kNCls; ++c) {
+      if (!p->L.totals[PH_PW][c]) continue;
+      set_phase(p, &a, PH_PW, c);
+      if ((e = launch_power(cls_prec(c), 1, a, st)) != hipSuccess) return hip_fail(e, "power matvec");
+    }
+    a.last = it == p->spectral_init - 1;
+    if ((e = launch_power(kF32, 2, a, st)) != hipSuccess) return hip_fail(e, "power norm");
+  }
+  return PE_OK;
+}
+
 pe_status enqueue_steps(const pe_plan* p, hipStream_t st, int fallback) {
+  if (p->fast_restart > 0) return enqueue_fast(p, st);
   pe_status s = enqueue_norm(p, st, fallback);
   if (s != PE_OK) return s;
-  for (int t = 0; t < p->T; ++t)
+  for (int t = 0; t < p->T + p->t0; ++t)
     for (int kind = 0; kind < 3; ++kind) {
+      if (t < p->t0 && kind == 1 && (s = enqueue_power(p, st)) != PE_OK) return s;
       if ((s = enqueue_gemm(p, t, kind, st, fallback)) != PE_OK) return s;
       if (p->learned && !fallback && t == 0 && kind == 1 && (s = enqueue_select(p, st)) != PE_OK)
         return s;
@@ -582,6 +744,13 @@ pe_status plan_init(pe_plan* p, int count, const pe_matrix* mats, const pe_opts*
   p->fp8_steps = o->compute == PE_COMPUTE_FP8 ? o->fp8_steps : 0;
   p->T = o->T;
   p->norm_mode = o->norm_mode;
+  p->spectral_init = o->spectral_init;
+  p->t0 = o->spectral_init > 0 ? 1 : 0;
+  p->muon_beta = o->muon_beta;
+  p->muon_lr = o->muon_lr;
+  p->muon_wd = o->muon_wd;
+  p->fast_restart = o->fast_restart;
+  p->fast_eps = o->fast_eps;
   p->abc.resize(3 * o->T);
   for (int i = 0; i < 3 * o->T; ++i) p->abc[i] = (float)o->abc[i];
   p->learned = learned_mode(o);
@@ -726,7 +895,7 @@ pe_status pe_plan_launch(pe_plan* p, void* stream, int32_t use_graph) {
 
 pe_status pe_plan_launch_phase(pe_plan* p, int32_t step, int32_t phase, void* stream) {
   g_last_error.clear();
-  if (!p || step < 0 || step >= p->T || phase < 0 || phase > 3) return PE_EINVAL;
+  if (!p || step < 0 || step >= p->T + p->t0 || phase < 0 || phase > 3) return PE_EINVAL;
   // a learned plan's step 1 also selects the class between its phases
   if (p->learned) return PE_EUNSUPPORTED;
   if (phase_total(p->L, PH_PREP) == 0) return PE_OK;

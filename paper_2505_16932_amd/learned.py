@@ -1,15 +1,19 @@
 """Training data and training loop of the l-predictor.
 
 The paper guesses l = 1e-3 for every matrix (Section 3.3).  The predictor
-picks, per matrix, one of eight schedules l in CLASS_ELL from moments of the
-step-1 Gram matrix.  Because the polar error of a polynomial iteration depends
-only on the normalised spectrum (Appendix C: ||polar(M) - p(M)||_2 =
-max_i |1 - p(sigma_i)|), training samples are (shape, spectrum) pairs:
+picks, per matrix, one of eight schedules from moments of the step-1 Gram
+matrix; a schedule is a pair (l, T') from CLASS_TABLE -- the greedy schedule
+for l run for T' <= T steps, the device skipping the matrix's later steps --
+so that matrices whose spectrum allows it finish early.  Because the polar
+error of a polynomial iteration depends only on the normalised spectrum
+(Appendix C: ||polar(M) - p(M)||_2 = max_i |1 - p(sigma_i)|), training
+samples are (shape, spectrum) pairs:
 
 * features: the 16 values the selection kernel computes on the device from
   s, L and m_k = sum_i sigma_hat_i^(2k), k = 1..4 (same formula, float64 here);
-* label: the class whose T-step schedule (from pe_coeffs) leaves the smallest
-  max_i |1 - phi_T(sigma_hat_i)|, ties to the larger l.
+* label: among the classes whose error max_i |1 - phi(sigma_hat_i)| does not
+  exceed the fixed class's (l = 1e-3, all T steps), the one with the fewest
+  steps, then the smallest error.
 
 Spectrum families follow the intended use (weight-gradient-like matrices):
 log-uniform on [10^-k, 1] (k ~ U[1, 6]), power law i^-gamma (gamma ~ U[0.3, 2]),
@@ -23,11 +27,18 @@ import numpy as np
 
 from . import CLASSES, FEATURES, FIXED_CLASS, MLP_PARAMS, MLPTrainer, coeffs
 
-CLASS_ELL = (1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5)
+# (l, T'), T' = None: all T steps; must match the library's class table
+CLASS_TABLE = ((1e-1, 2), (1e-1, 3), (3e-2, 3), (1e-2, 4), (1e-3, None), (3e-3, 4), (3e-4, None),
+               (1e-4, None))
+CLASS_ELL = tuple(c[0] for c in CLASS_TABLE)
+
+
+def class_steps(T: int) -> np.ndarray:
+    return np.array([T if k is None else min(T, k) for _, k in CLASS_TABLE])
 
 
 def class_schedules(T: int):
-    return [coeffs(l, T).abc for l in CLASS_ELL]
+    return [coeffs(l, int(k)).abc for (l, _), k in zip(CLASS_TABLE, class_steps(T))]
 
 
 def _phi(abc_list, x):
@@ -80,15 +91,18 @@ def label_errors(sig_hat, scheds):
     return np.array([np.max(np.abs(1.0 - _phi(abc, sig_hat))) for abc in scheds])
 
 
-def best_class(errs, rtol=1e-9):
+def best_class(errs, steps, rtol=1e-9):
+    """Fewest steps within the fixed class's error, then the smallest error."""
     errs = np.asarray(errs)
-    return int(np.flatnonzero(errs <= np.min(errs) * (1 + rtol) + 1e-15)[0])
+    ok = [c for c in range(len(errs)) if errs[c] <= errs[FIXED_CLASS] * (1 + rtol) + 1e-15]
+    return min(ok, key=lambda c: (steps[c], errs[c], c))
 
 
 def build_dataset(n: int, seed: int, T: int):
     """features [n x 16] float32, labels [n] int32, per-class errors [n x 8]."""
     rng = np.random.Generator(np.random.PCG64(seed))
     scheds = class_schedules(T)
+    steps = class_steps(T)
     F = np.zeros((n, FEATURES), dtype=np.float32)
     Y = np.zeros(n, dtype=np.int32)
     E = np.zeros((n, CLASSES))
@@ -99,7 +113,7 @@ def build_dataset(n: int, seed: int, T: int):
         mom = (np.sum(s2), np.sum(s2 ** 2), np.sum(s2 ** 3), np.sum(s2 ** 4))
         F[i] = features(min(m, k), max(m, k), mom)
         E[i] = label_errors(sh, scheds)
-        Y[i] = best_class(E[i])
+        Y[i] = best_class(E[i], steps)
     return F, Y, E
 
 
@@ -139,18 +153,20 @@ def train(F, Y, epochs: int = 30, batch: int = 1024, lr: float = 3e-3, seed: int
     return params
 
 
-def evaluate(params, F, E, device="cuda"):
-    """Mean and median per-sample error of the chosen class vs the fixed class."""
+def evaluate(params, F, E, T: int, Y=None, device="cuda"):
+    """Steps and per-sample error of the chosen classes against the fixed class."""
     import torch
     from . import mlp_forward
     logits = mlp_forward(params, torch.from_numpy(np.ascontiguousarray(F, dtype=np.float32)).to(device))
     cls = logits.argmax(dim=1).cpu().numpy()
+    steps = class_steps(T)
     chosen = E[np.arange(len(cls)), cls]
     fixed = E[:, FIXED_CLASS]
-    best = E.min(axis=1)
-    return dict(mean_chosen=float(chosen.mean()), mean_fixed=float(fixed.mean()),
-                mean_best=float(best.mean()), median_chosen=float(np.median(chosen)),
-                median_fixed=float(np.median(fixed)),
+    worse = chosen > fixed * (1 + 1e-9) + 1e-15
+    return dict(mean_steps=float(steps[cls].mean()), fixed_steps=float(T),
+                mean_chosen=float(chosen.mean()), mean_fixed=float(fixed.mean()),
+                frac_fewer_steps=float(np.mean(steps[cls] < T)),
                 frac_better=float(np.mean(chosen < fixed - 1e-12)),
-                frac_worse=float(np.mean(chosen > fixed + 1e-12)),
-                accuracy=float(np.mean(cls == E.argmin(axis=1))), classes=cls)
+                frac_worse=float(np.mean(worse)),
+                mean_excess_when_worse=float((chosen - fixed)[worse].mean()) if worse.any() else 0.0,
+                accuracy=float(np.mean(cls == Y)) if Y is not None else None, classes=cls)

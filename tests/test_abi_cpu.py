@@ -83,7 +83,8 @@ def test_coeffs_invalid_arguments():
 
 def _opts(T=5, compute=1, fp8=0):
     abc = np.tile(np.array(S.NS5), (T, 1)).reshape(-1).copy()
-    o = pe.Opts(T, abc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), compute, fp8, 0, 0, None, -1, 0.0)
+    o = pe.Opts(T, abc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), compute, fp8, 0, 0, None, -1, 0.0,
+                0, 0, 0.0, 0.0, 0.0, 0.0, 0)
     return o, abc
 
 
@@ -141,7 +142,10 @@ def test_learned_labels_match_oracle():
         # the two schedule builders differ by up to ~1e-7 relative on the
         # near-degenerate steps of the larger-l schedules (4x4 conditioning)
         assert np.allclose(E[i], e, rtol=1e-6, atol=1e-8)
-        assert e[Y[i]] <= e.min() * (1 + 1e-6) + 1e-8
+        # the label: fewest steps within the fixed class's error (the oracle's rule)
+        steps = OM.class_steps(5)
+        assert e[Y[i]] <= e[OM.FIXED_CLASS] * (1 + 1e-6) + 1e-8
+        assert steps[Y[i]] == steps[OM.label(e, steps)]
         assert np.allclose(F[i], OM.features(min(m, n), max(m, n), OM.moments_from_spectrum(sh)),
                            rtol=1e-5, atol=1e-5)
 
@@ -158,7 +162,7 @@ def test_tile_table_drives_the_tile_choice(tmp_path):
     t = tmp_path / "tab.txt"
     sizes = {}
     for tile in (1, 2):
-        # a single-matrix call looks up the class's _x1 regime
+        # a call below 3e12 FLOP per step looks up the class's _x1 regime
         t.write_text(f"# test\n{cls}_x1 {tile}  # comment\n{cls}_xN {3 - tile}\n")
         assert L.pe_tile_table_load(str(t).encode()) == 0
         sizes[tile] = L.pe_workspace_size(1, ctypes.byref(m), ctypes.byref(o))
@@ -175,3 +179,15 @@ def test_tile_table_drives_the_tile_choice(tmp_path):
     shipped = os.path.join(os.path.dirname(pe.LIB_PATH), "tile_table.txt")
     t.write_text("# empty\n")
     assert L.pe_tile_table_load((shipped if os.path.exists(shipped) else str(t)).encode()) == 0
+
+
+@pytest.mark.parametrize("ell,T", [(1e-3, 8), (1e-2, 6), (0.2, 4)])
+def test_cubic_coeffs_match_oracle(ell, T):
+    c = pe.coeffs_cubic(ell, T)
+    o = S.greedy_schedule_cubic(ell, T)
+    assert np.allclose(c.abc, o.abc, rtol=1e-13, atol=1e-15)
+    assert np.all(c.abc[:, 2] == 0.0)
+    assert np.allclose(c.bounds[:, 0], o.ell, rtol=1e-12)
+    assert abs(c.err_bound - o.err_bound) <= 1e-12
+    c1 = pe.coeffs_cubic(ell, T, safety=1.0)
+    assert np.allclose(c1.abc, S.greedy_schedule_cubic(ell, T, safety=1.0).abc, rtol=1e-13)

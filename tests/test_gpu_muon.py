@@ -1,0 +1,99 @@
+"""The fused Muon step (Section 1.1) through the C ABI against the oracle's
+step in FP64 on the same values: the momentum update in the norm pass, the
+weight step in the last update's epilogue, the iteration running on the new
+momentum.  FP32 compute: the momentum to FP32 rounding and the step direction
+(W - W') / lr within 1e-5; bf16: the direction within 3e-2 and bf16 weights
+within a few bf16 ulps of the oracle's."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import muon as MU
+from tests.gpu_util import device_input, oracle_schedule, relf, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pe():
+    import paper_2505_16932_amd as pe
+    pe.lib()
+    return pe
+
+
+def _state(shape, seed, torch, wdtype):
+    r = synth.rng(seed)
+    G, gvals = device_input(synth.powerlaw(seed, *shape).G * 3.0, torch.bfloat16)
+    M = torch.from_numpy((0.02 * r.standard_normal(shape)).astype(np.float32)).cuda()
+    W = torch.from_numpy(r.standard_normal(shape).astype(np.float32)).to(wdtype).cuda()
+    return G, gvals, M, W
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_muon_step_matches_oracle(pe, compute):
+    import torch
+    shapes = [(300, 700), (700, 300), (768, 2304)]
+    lr, beta, wd = (1.0, 0.9, 0.0) if compute == "f32" else (1.0, 0.95, 0.1)
+    abc = oracle_schedule(5)
+    Gs, gv, Ms, Ws = [], [], [], []
+    for k, sh in enumerate(shapes):
+        G, g, M, W = _state(sh, 1500 + k, torch, torch.float32)
+        Gs.append(G); gv.append(g); Ms.append(M); Ws.append(W)
+    M0 = [to_np(M) for M in Ms]
+    W0 = [to_np(W) for W in Ws]
+    outs = pe.muon_step(Gs, Ms, Ws, lr=lr, beta=beta, wd=wd, T=5, abc=abc, compute=compute)
+    torch.cuda.synchronize()
+    assert all(o is None for o in outs)
+    bar = 1e-5 if compute == "f32" else 3e-2
+    for k in range(len(shapes)):
+        Mr, Xr, Wr = MU.muon_step(gv[k], M0[k], W0[k], abc, lr=lr, beta=beta, wd=wd)
+        em = relf(to_np(Ms[k]), Mr)
+        direction = ((1 - lr * wd) * W0[k] - to_np(Ws[k])) / lr
+        ex = relf(direction, Xr)
+        print(f"[muon] {compute} {shapes[k]} momentum relF={em:.2e} direction relF={ex:.3e}", flush=True)
+        assert em <= 1e-6
+        assert ex <= bar
+
+
+def test_muon_bf16_weights_and_output(pe):
+    """bf16 weights updated in place; the output X is written as well when given."""
+    import torch
+    abc = oracle_schedule(5)
+    G, g, M, W = _state((512, 1024), 1510, torch, torch.bfloat16)
+    M0, W0 = to_np(M), to_np(W)
+    X = torch.empty((512, 1024), dtype=torch.float32, device="cuda")
+    pe.muon_step([G], [M], [W], lr=0.02, beta=0.9, T=5, abc=abc, compute="bf16", outs=[X])
+    torch.cuda.synchronize()
+    Mr, Xr, Wr = MU.muon_step(g, M0, W0, abc, lr=0.02, beta=0.9)
+    assert relf(to_np(X), Xr) <= 3e-2
+    # W' = bf16(W - lr X): within a bf16 rounding of the oracle's W' plus lr |dX|
+    d = np.abs(to_np(W) - Wr)
+    assert np.all(d <= 2.0 ** -8 * np.abs(Wr) + 0.02 * 0.05 + 1e-6)
+
+
+def test_muon_plan_replays_are_successive_steps(pe):
+    """A plan captured with the Muon fields applies one step per launch: two
+    launches equal two oracle steps with the same gradient."""
+    import torch
+    abc = oracle_schedule(5)
+    G, g, M, W = _state((256, 640), 1520, torch, torch.float32)
+    M0, W0 = to_np(M), to_np(W)
+    plan = pe.Plan([G], outs=[None], T=5, abc=abc, compute="f32", moms=[M], weights=[W],
+                   muon=(0.9, 1.0, 0.0))
+    plan.launch(graph=True)
+    plan.launch(graph=True)
+    torch.cuda.synchronize()
+    M1, _, W1 = MU.muon_step(g, M0, W0, abc, lr=1.0, beta=0.9)
+    M2, X2, W2 = MU.muon_step(g, M1, W1, abc, lr=1.0, beta=0.9)
+    assert relf(to_np(M), M2) <= 1e-6
+    assert relf(W1 - to_np(W), X2) <= 1e-5
+    plan.close()
+
+
+def test_muon_rejects_fallback_combination(pe):
+    import torch
+    G = torch.ones((64, 128), dtype=torch.bfloat16, device="cuda")
+    M = torch.zeros((64, 128), dtype=torch.float32, device="cuda")
+    with pytest.raises(pe.PEError) as ei:
+        pe.polar_batched([G], T=5, moms=[M], muon=(0.9, 0.1, 0.0), force_class=4, fallback_tau=0.1)
+    assert ei.value.status == 2
