@@ -192,7 +192,12 @@ typedef struct {
  * 256-byte aligned; its contents need no initialisation. */
 size_t pe_workspace_size(int32_t count, const pe_matrix* mats, const pe_opts* opts);
 
-/* One matrix: X = PolarExpress(G).  Asynchronous on `stream`. */
+/* One matrix: X = PolarExpress(G).  Asynchronous on `stream`.  A zero G
+ * gives a zero X (the 1e-7 guard of the normalisation).  Values are not
+ * checked (the call does not synchronise): a NaN or infinite entry makes the
+ * matrix's norm, and so its whole X, NaN, and in a batched call only that
+ * matrix's; finite entries must keep the FP32 per-tile sums of squares of the
+ * norm pass finite (|g| below about 1e17). */
 pe_status pe_polar(const pe_matrix* mat, const pe_opts* opts, void* ws, size_t ws_bytes,
                    void* stream);
 
@@ -249,11 +254,13 @@ pe_status pe_plan_launch_phase(pe_plan* plan, int32_t step, int32_t phase, void*
 pe_status pe_quantize_e4m3(const void* x, int32_t x_dtype, void* q, int64_t n, float scale,
                            void* stream);
 
-/* After a learned call (plan launched and synchronised): per matrix the class
- * used, the 16 features, the ||X X^T - I||_2 estimate and the fallback flag
- * (host outputs, each nullable; classes/flags count ints, feats count*16 and
- * est count floats).  Synchronous copy from the plan's workspace. */
-pe_status pe_plan_selection(pe_plan* plan, int32_t* classes, float* feats, float* est,
+/* After a learned plan's launch: per matrix the class used, the 16 features,
+ * the ||X X^T - I||_2 estimate and the fallback flag (host outputs, each
+ * nullable; classes/flags count ints, feats count*16 and est count floats;
+ * an empty matrix reports class -1).  One copy from the plan's workspace,
+ * ordered on `stream` after the work already queued there (the launch's
+ * stream), then a synchronisation of that stream only. */
+pe_status pe_plan_selection(pe_plan* plan, void* stream, int32_t* classes, float* feats, float* est,
                             int32_t* flags);
 
 /* ---------------------------------------------------------------------------

@@ -123,7 +123,7 @@ def lib() -> ctypes.CDLL:
                                        ctypes.c_int64, ctypes.c_float, ctypes.c_void_p]
         L.pe_plan_selection.restype = ctypes.c_int
         L.pe_plan_selection.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                        ctypes.c_void_p, ctypes.c_void_p]
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.pe_mlp_workspace_size.restype = ctypes.c_size_t
         L.pe_mlp_workspace_size.argtypes = [ctypes.c_int32]
         L.pe_mlp_forward.restype = ctypes.c_int
@@ -530,15 +530,16 @@ class Plan:
         _check(lib().pe_plan_launch(self._h, _stream(stream), 1 if graph else 0), "pe_plan_launch")
         return self.outs
 
-    def selection(self):
-        """(classes, features, estimates, fallback flags) of a learned plan's last launch."""
+    def selection(self, stream=None):
+        """(classes, features, estimates, fallback flags) of a learned plan's last
+        launch, read on ``stream`` (the launch's; default the current stream)."""
         n = len(self.Gs)
         cls = np.zeros(n, dtype=np.int32)
         flags = np.zeros(n, dtype=np.int32)
         feats = np.zeros((n, FEATURES), dtype=np.float32)
         est = np.zeros(n, dtype=np.float32)
-        _check(lib().pe_plan_selection(self._h, cls.ctypes.data, feats.ctypes.data, est.ctypes.data,
-                                       flags.ctypes.data), "pe_plan_selection")
+        _check(lib().pe_plan_selection(self._h, _stream(stream), cls.ctypes.data, feats.ctypes.data,
+                                       est.ctypes.data, flags.ctypes.data), "pe_plan_selection")
         return cls, feats, est, flags
 
     def launch_phase(self, step: int, phase: int, stream=None):

@@ -1336,7 +1336,7 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
       float t = 0.0f;
 #pragma unroll
       for (int w = 0; w < W::NW; ++w) t += rf[k * W::NW + w];
-      d.mom[(size_t)tileid * 4 + k] = (double)(k == 0 ? t : wgt * t);
+      d.mom[(size_t)tileid * 4 + k] = k == 0 ? t : wgt * t;
     }
   }
 }
@@ -1368,23 +1368,33 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
   void* XTn = (args.t & 1) ? d.XT0 : d.XT1;
   float amax = 0.0f;
   if (stage_out) __syncthreads();  // every wave is done with the operand ring
-  // FP32 inputs prefetched one fragment ahead (16 values per lane)
-  float pre[2][C::RG][4];
-  auto load_piece = [&](int fm, int fn, float (&dst)[C::RG][4]) {
+  // FP32 inputs prefetched one piece ahead: 16 values per lane, i.e. one
+  // fragment of the 256 tile (four row groups) or a fragment row of the 128
+  // tile (FN fragments of one row group); a whole fragment row of the 256 tile
+  // would spill
+  constexpr int PF = BT == 256 ? 1 : FN;  // fragments per piece
+  constexpr int NPIECE = 4 * FN / PF;
+  float pre[2][PF][C::RG][4];
+  auto load_piece = [&](int u, float (&dst)[PF][C::RG][4]) {
+    const int fm = u * PF / FN, fn0 = u * PF % FN;
 #pragma unroll
-    for (int g = 0; g < C::RG; ++g) {
-      const size_t o = (size_t)(tm * BT + acc_row<BT>(wm, fm, g, lane)) * Lp + tn * BT + acc_col<P, BT>(wn, fn, lane);
+    for (int f = 0; f < PF; ++f)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dst[g][r] = load_as_float<kStream>(d.Xf + o + (size_t)r * Lp);
-    }
+      for (int g = 0; g < C::RG; ++g) {
+        const size_t o = (size_t)(tm * BT + acc_row<BT>(wm, fm, g, lane)) * Lp + tn * BT +
+                         acc_col<P, BT>(wn, fn0 + f, lane);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[f][g][r] = load_as_float<kStream>(d.Xf + o + (size_t)r * Lp);
+      }
   };
-  load_piece(0, 0, pre[0]);
+  load_piece(0, pre[0]);
 #pragma unroll
-  for (int u = 0; u < 4 * FN; ++u) {
-    const int fm = u / FN, fn = u % FN;
-    if (u + 1 < 4 * FN) load_piece((u + 1) / FN, (u + 1) % FN, pre[(u + 1) & 1]);
-    const float (&cur)[C::RG][4] = pre[u & 1];
-    {
+  for (int u = 0; u < NPIECE; ++u) {
+    if (u + 1 < NPIECE) load_piece(u + 1, pre[(u + 1) & 1]);
+#pragma unroll
+    for (int f = 0; f < PF; ++f) {
+      const int fm = u * PF / FN, fn = u * PF % FN + f;
+      const float (&cur)[C::RG][4] = pre[u & 1][f];
 #pragma unroll
       for (int g = 0; g < C::RG; ++g) {
         const int i = tm * BT + acc_row<BT>(wm, fm, g, lane);

@@ -179,28 +179,29 @@ __global__ void mlp_reduce_kernel(const float* part, const float* part_loss, int
 }
 
 // ----------------------------------------------------- features and selection
-// Must agree with the host feature code used for training (learned.py).
-__device__ void features_from_moments(int s, int L, const double* m, float* f) {
-  const double m1 = fmax(m[0], 1e-300), m2 = fmax(m[1], 1e-300), m3 = fmax(m[2], 1e-300),
-               m4 = fmax(m[3], 1e-300);
-  const double ls = log((double)(s > 1 ? s : 1)), lL = log((double)(L > 1 ? L : 1));
-  const double l1 = log(m1), l2 = log(m2), l3 = log(m3), l4 = log(m4);
-  const double den = fmax(ls, 1e-3);
-  f[0] = (float)(ls / 8.0);
-  f[1] = (float)(lL / 8.0);
-  f[2] = (float)(lL - ls);
-  f[3] = (float)l1;
-  f[4] = (float)(l2 / 4.0);
-  f[5] = (float)(l3 / 8.0);
-  f[6] = (float)(l4 / 8.0);
-  f[7] = (float)((2 * l1 - l2) / den);
-  f[8] = (float)((2 * l2 - l4) / den);
-  f[9] = (float)(l1 + l3 - 2 * l2);
-  f[10] = (float)(l2 + l4 - 2 * l3);
-  f[11] = (float)(l4 / 8.0 - l1 / 2.0);
-  f[12] = (float)((2 * l1 - l2) / 8.0);
-  f[13] = (float)((2 * l2 - l4) / 8.0);
-  f[14] = (float)(ls - (2 * l1 - l2));
+// Must agree with the host feature code used for training (learned.py); FP32
+// here (FP64 on the device is kept to the norm's cross-block sum).
+__device__ void features_from_moments(int s, int L, const float* m, float* f) {
+  const float m1 = fmaxf(m[0], 1e-37f), m2 = fmaxf(m[1], 1e-37f), m3 = fmaxf(m[2], 1e-37f),
+              m4 = fmaxf(m[3], 1e-37f);
+  const float ls = logf((float)(s > 1 ? s : 1)), lL = logf((float)(L > 1 ? L : 1));
+  const float l1 = logf(m1), l2 = logf(m2), l3 = logf(m3), l4 = logf(m4);
+  const float den = fmaxf(ls, 1e-3f);
+  f[0] = ls / 8.0f;
+  f[1] = lL / 8.0f;
+  f[2] = lL - ls;
+  f[3] = l1;
+  f[4] = l2 / 4.0f;
+  f[5] = l3 / 8.0f;
+  f[6] = l4 / 8.0f;
+  f[7] = (2.0f * l1 - l2) / den;
+  f[8] = (2.0f * l2 - l4) / den;
+  f[9] = l1 + l3 - 2.0f * l2;
+  f[10] = l2 + l4 - 2.0f * l3;
+  f[11] = l4 / 8.0f - l1 / 2.0f;
+  f[12] = (2.0f * l1 - l2) / 8.0f;
+  f[13] = (2.0f * l2 - l4) / 8.0f;
+  f[14] = ls - (2.0f * l1 - l2);
   f[15] = 1.0f;
 }
 
@@ -208,22 +209,22 @@ __device__ void features_from_moments(int s, int L, const double* m, float* f) {
 // argmax (first maximum wins, i.e. the larger l on ties), store the class.
 __global__ __launch_bounds__(64) void select_kernel(KArgs args) {
   __shared__ float P[kMlpParams];
-  __shared__ double red[4][64];
+  __shared__ float red[4][64];
   if (args.mlp)
     for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) P[i] = args.mlp[i];
   __syncthreads();
   for (int mi = blockIdx.x; mi < args.count; mi += gridDim.x) {
     const MatDesc& d = args.descs[mi];
     if (!d.selp) continue;
-    double acc[4] = {0, 0, 0, 0};
+    float acc[4] = {0, 0, 0, 0};
     for (int u = threadIdx.x; u < d.syrk_nt; u += blockDim.x)
       for (int k = 0; k < 4; ++k) acc[k] += d.mom[(size_t)u * 4 + k];
     for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
     __syncthreads();
     if (threadIdx.x == 0) {
-      double m[4];
+      float m[4];
       for (int k = 0; k < 4; ++k) {
-        double t = 0.0;
+        float t = 0.0f;
         for (int i = 0; i < 64; ++i) t += red[k][i];
         m[k] = t;
       }

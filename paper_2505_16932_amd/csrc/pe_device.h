@@ -75,7 +75,7 @@ struct MatDesc {
   int32_t* selp;    // schedule class of this matrix
   int32_t* flagp;   // 1: the fallback re-run recomputes this matrix
   float* A2f;       // sp x sp fp32: A^2 of step 1, before the class is known
-  double* mom;      // [syrk_nt][4] per-tile partial moments tr(A^k), k = 1..4
+  float* mom;       // [syrk_nt][4] per-tile partial moments tr(A^k), k = 1..4
   float* feat;      // [16] features (diagnostic copy)
   float* est;       // [2]: estimate of ||X X^T - I||_2, flag
   float* vec;       // power iteration vectors: v [sp], y [sp], w [Lp]

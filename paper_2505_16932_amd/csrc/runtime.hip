@@ -70,7 +70,12 @@ constexpr int kGemmGridCapLarge = 256;  // 256-tile kernel: 1 resident block per
 constexpr int kPrepGridCap = 2048;
 constexpr int kReduceGridCap = 1024;
 constexpr int kQuantGridCap = 2048;
-constexpr int kFillTarget = 512;     // Gram-side items wanted per launch
+// Gram-side items wanted per launch before split-K kicks in.  Split-K buys
+// parallelism with FP32 partial tiles written and summed by a second launch;
+// measured on a single 4096 x 1024 bf16 matrix (36 Gram tiles of 128), splits
+// of 15 / 8 / 4 / 2 / 1 gave 0.83 / 0.68 / 0.58 / 0.55 / 0.58 ms per call, so
+// the target stays low: a couple of splits for calls with tens of tiles.
+constexpr int kFillTarget = 64;
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -107,7 +112,13 @@ struct Layout {
   std::vector<int32_t> ord_gram[kNCls];
   size_t bytes = 0;
   size_t descs_off = 0, offs_off = 0, coef_off = 0;
+  size_t sel_off = 0;  // learned plans: kSelWords words per matrix (class, flag, features, estimate)
 };
+
+// per-matrix selection record of a learned plan, contiguous over the matrices
+// so pe_plan_selection reads all of them with one copy: words 0-15 class and
+// fallback flag, 16-31 the 16 features, 32-47 the estimate
+constexpr int kSelWords = 48;
 
 bool valid_matrix(const pe_matrix& m) {
   if (m.m < 0 || m.n < 0) return false;
@@ -264,6 +275,8 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
   const bool learned = learned_mode(o);
   L->coef_off = off;
   if (learned) off = align_up(off + sizeof(float) * kClasses * 3 * (size_t)o->T + sizeof(int32_t) * kClasses);
+  L->sel_off = off;
+  if (learned) off = align_up(off + sizeof(int32_t) * kSelWords * (size_t)std::max(count, 1));
   for (int i = 0; i < count; ++i) {
     const pe_matrix& m = mats[i];
     const Shape& q = sh[i];
@@ -342,13 +355,13 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
         for (int k = 0; k < 6; ++k) d.fb[k] = (float*)take(A * 4);
       if (o->spectral_init > 0 && !learned) d.vec = (float*)take(((size_t)2 * q.sp + q.Lp) * 4);
       if (learned) {
-        int32_t* ints = (int32_t*)take(64);
-        d.selp = ints;
-        d.flagp = ints ? ints + 1 : nullptr;
+        int32_t* rec = ws ? (int32_t*)(ws + L->sel_off) + (size_t)i * kSelWords : nullptr;
+        d.selp = rec;
+        d.flagp = rec ? rec + 1 : nullptr;
+        d.feat = rec ? (float*)(rec + 16) : nullptr;
+        d.est = rec ? (float*)(rec + 32) : nullptr;
         d.A2f = (float*)take(A * 4);
-        d.mom = (double*)take((size_t)q.syrk * 4 * 8);
-        d.feat = (float*)take(kFeat * 4);
-        d.est = (float*)take(64);
+        d.mom = (float*)take((size_t)q.syrk * 4 * 4);
         d.vec = (float*)take(((size_t)2 * q.sp + q.Lp) * 4);
       }
     }
@@ -913,26 +926,28 @@ pe_status pe_plan_destroy(pe_plan* p) {
   return PE_OK;
 }
 
-pe_status pe_plan_selection(pe_plan* p, int32_t* classes, float* feats, float* est, int32_t* flags) {
+pe_status pe_plan_selection(pe_plan* p, void* stream, int32_t* classes, float* feats, float* est,
+                            int32_t* flags) {
   g_last_error.clear();
   if (!p) return PE_EINVAL;
   if (!p->learned) return PE_EINVAL;
-  hipError_t e = hipDeviceSynchronize();
-  if (e != hipSuccess) return hip_fail(e, "selection sync");
+  if (p->count == 0) return PE_OK;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<int32_t> rec((size_t)p->count * kSelWords);
+  const char* src = (const char*)p->d_descs - p->L.descs_off + p->L.sel_off;
+  hipError_t e = hipMemcpyAsync(rec.data(), src, rec.size() * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "selection copy");
   for (int i = 0; i < p->count; ++i) {
-    const MatDesc& d = p->L.descs[i];
-    int32_t ints[2] = {-1, 0};
-    float f[kFeat] = {0}, es[2] = {0, 0};
-    if (d.selp) {
-      if ((e = hipMemcpy(ints, d.selp, sizeof ints, hipMemcpyDeviceToHost)) != hipSuccess ||
-          (e = hipMemcpy(f, d.feat, sizeof f, hipMemcpyDeviceToHost)) != hipSuccess ||
-          (e = hipMemcpy(es, d.est, sizeof es, hipMemcpyDeviceToHost)) != hipSuccess)
-        return hip_fail(e, "selection copy");
+    const int32_t* r = rec.data() + (size_t)i * kSelWords;
+    const bool run = p->L.descs[i].syrk_nt > 0;  // empty matrices have no record
+    if (classes) classes[i] = run ? r[0] : -1;
+    if (flags) flags[i] = run ? r[1] : 0;
+    if (feats) {
+      if (run) memcpy(feats + (size_t)i * kFeat, r + 16, kFeat * 4);
+      else memset(feats + (size_t)i * kFeat, 0, kFeat * 4);
     }
-    if (classes) classes[i] = ints[0];
-    if (flags) flags[i] = ints[1];
-    if (feats) memcpy(feats + (size_t)i * kFeat, f, sizeof f);
-    if (est) est[i] = es[0];
+    if (est) est[i] = run ? *(const float*)(r + 32) : 0.0f;
   }
   return PE_OK;
 }

@@ -116,7 +116,8 @@ def test_training_gain_over_fixed_ell(pe, trained):
 def test_selection_in_plan_matches_oracle(pe, trained):
     """Matrices with known spectra: GPU features from the step-1 Gram moments vs
     the oracle's features of the normalised spectrum; the class vs the oracle MLP
-    on the GPU's features; the result vs a plain call with that class's schedule."""
+    on the GPU's features; the result vs a plain call with that class's schedule
+    (split-K off on both sides, so that the two sum in the same order)."""
     import torch
     cases = [(300, 900, np.geomspace(1, 1e-5, 300)), (512, 512, synth.spectrum_powerlaw(512, 0.5)),
              (640, 200, np.linspace(1.0, 0.4, 200)), (256, 1536, synth.spectrum_powerlaw(256, 1.5))]
@@ -126,7 +127,8 @@ def test_selection_in_plan_matches_oracle(pe, trained):
         Gs.append(g)
         vals.append(v)
     abc4 = OS.greedy_schedule(1e-3, 5).abc
-    plan = pe.Plan(Gs, T=5, abc=abc4, compute="bf16", predictor=trained, out_dtype=torch.float32)
+    plan = pe.Plan(Gs, T=5, abc=abc4, compute="bf16", predictor=trained, out_dtype=torch.float32,
+                   split_k=1)
     plan.launch(graph=False)
     torch.cuda.synchronize()
     cls, feats, est, flags = plan.selection()
@@ -141,7 +143,7 @@ def test_selection_in_plan_matches_oracle(pe, trained):
         logits, _ = OM.forward(theta, feats[k:k + 1].astype(np.float64))
         assert int(np.argmax(logits[0])) == cls[k]
         Tc, abcc = class_schedule(pe, int(cls[k]), abc4)
-        Y = pe.polar(Gs[k], T=Tc, abc=abcc, compute="bf16", out_dtype=torch.float32)
+        Y = pe.polar(Gs[k], T=Tc, abc=abcc, compute="bf16", out_dtype=torch.float32, split_k=1)
         torch.cuda.synchronize()
         assert relf(to_np(plan.outs[k]), to_np(Y)) <= 1e-6
     plan.close()
