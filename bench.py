@@ -29,6 +29,9 @@ power iteration on the device), its prediction from the scalar composite on
 the known spectrum (max_i |1 - phi_T(sigma_i / (1.01 ||G||_F))|), and the
 relative Frobenius distance of the GPU result from the FP64 oracle's same
 iteration on the matrix the CPU baseline runs.
+fast_rect_f32 (wide workloads): the rectangular fast iteration (restart every
+3 steps) against the standard iteration, both FP32, on three 4096x14336
+matrices: ms per call and the polar error of each result.
 
 Prints ONE JSON line (rank 0, N = 1).
 """
@@ -255,6 +258,33 @@ def cpu_baseline(G_cpu64, abc, T):
                 sample=f"1 of the workload's matrices ({m}x{n}), T={T}, FP64 NumPy, {dt:.1f} s"), ref
 
 
+def fast_row(Gs, meta, abc, T, args, stream, torch, log):
+    """The rectangular fast iteration (restart every 3 steps, no shift) against
+    the standard iteration, both FP32, on the three 4096x14336 matrices of the
+    first layer: ms per call and the polar error of every result."""
+    import paper_2505_16932_amd as pe
+    idx = [i for i, G in enumerate(Gs) if max(G.shape) >= 3 * min(G.shape)][:3]
+    sub = [Gs[i] for i in idx]
+    fl = algo_flops([tuple(G.shape) for G in sub], T)
+    row = dict(matrices=len(sub), shape=list(sub[0].shape), T=T, compute="f32", restart=3, eps=0.0)
+    for name, kw in (("standard", {}), ("fast", dict(fast_restart=3, fast_eps=0.0))):
+        plan = pe.Plan(sub, T=T, abc=abc, compute="f32", **kw)
+        ms, _ = time_plan(plan, max(2, min(args.steps, 5)), 1, stream, torch)
+        plan.launch(graph=True)
+        torch.cuda.synchronize()
+        errs = [spec_norm_factored(plan.outs[k], *factors(meta, i), torch) for k, i in enumerate(idx)]
+        row[name] = dict(ms_per_call=round(ms, 3), algorithmic_tflops=round(fl / (ms * 1e-3) / 1e12, 2),
+                         polar_err=[round(e, 5) for e in errs])
+        plan.close()
+        del plan
+        torch.cuda.empty_cache()
+    row["speedup"] = round(row["standard"]["ms_per_call"] / row["fast"]["ms_per_call"], 3)
+    log(f"[bench] fast rectangular iteration (FP32, {len(sub)} x {tuple(sub[0].shape)}): "
+        f"{row['fast']['ms_per_call']} ms against {row['standard']['ms_per_call']} ms "
+        f"(polar error {row['fast']['polar_err']} vs {row['standard']['polar_err']})")
+    return row
+
+
 def rel_fro_np(X, ref):
     import numpy as np
     return float(np.linalg.norm(X - ref) / np.linalg.norm(ref))
@@ -274,9 +304,13 @@ def main():
                     help="skip the e4m3 variant timed after the main plan (wide batches)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-fast-row", action="store_true",
+                    help="skip the FP32 standard-vs-fast rectangular iteration row")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--phase-reps", type=int, default=10)
     ap.add_argument("--tile", type=int, default=0, help="0 auto, 1 = 128x128, 2 = 256x256 block tile")
+    ap.add_argument("--split-k", type=int, default=0,
+                    help="0 auto; k >= 1 caps the Gram-side split-K factor (1 = no split)")
     ap.add_argument("--inputs", default="spectral", choices=["spectral", "gaussian"],
                     help="gaussian: iid inputs of the same shapes (profiler runs; no polar error)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -335,7 +369,8 @@ def main():
         return 100.0 * ((flops - f8) / (PEAK_BF16_TFLOPS * 1e12) +
                         f8 / (PEAK_FP8_TFLOPS * 1e12)) / (ms * 1e-3)
 
-    plan = pe.Plan(Gs, T=T, abc=abc, compute=args.compute, fp8_steps=args.fp8_steps, tile=args.tile)
+    plan = pe.Plan(Gs, T=T, abc=abc, compute=args.compute, fp8_steps=args.fp8_steps, tile=args.tile,
+                   split_k=args.split_k)
     log(f"[bench] plan ready ({args.compute}), workspace {plan.ws_bytes / 2**30:.1f} GiB")
     ms, wall_ms = time_plan(plan, args.steps, args.warmup, stream, torch)
     tflops = flops / (ms * 1e-3) / 1e12
@@ -415,6 +450,9 @@ def main():
         del outs
         torch.cuda.empty_cache()
 
+    if args.workload in ("wide-batch", "wide-layer") and not args.no_fast_row and "mats" in meta:
+        extra["fast_rect_f32"] = fast_row(Gs, meta, abc, T, args, stream, torch, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         G64 = Gs[ref_idx].to(torch.float64).cpu().numpy()
@@ -443,6 +481,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "matrices": len(Gs), "T": T, "ell": 1e-3,
                    "compute": args.compute, "fp8_steps": args.fp8_steps, "tile": args.tile,
+                   "split_k": args.split_k,
                    "shapes": sorted(set(shapes))},
         "pct_bf16_peak": round(100.0 * tflops / peak, 2),
         "pct_mfma_peak": round(pct_mfma(ms, args.fp8_steps if args.compute == "fp8" else 0), 2),
