@@ -49,7 +49,11 @@ typedef enum { PE_F32 = 0, PE_BF16 = 1 } pe_dtype;
 /* Arithmetic of the online stage.
  *  PE_COMPUTE_F32 : FP32 operands on FP32 MFMA, FP32 accumulation.
  *  PE_COMPUTE_BF16: FP32 master iterate; bf16 MFMA operands (X, A, B);
- *                   FP32 accumulation and FP32 epilogues.
+ *                   FP32 accumulation and FP32 epilogues.  Every path
+ *                   evaluates the update as (a_t + beta) X + (B - beta I) X,
+ *                   beta = tr(B) / s (the same polynomial; it moves the part
+ *                   of B X that cancels against a_t X out of the bf16 product).
+ *                   Matrices with min(m, n) < 16 run with FP32 operands.
  *  PE_COMPUTE_FP8 : as BF16, but in the first `fp8_steps` steps the two
  *                   Gram-side products (X X^T and A A^T) take OCP e4m3
  *                   operands with one per-tensor scale each (amax -> 448),

@@ -158,13 +158,13 @@ pe_status check_opts(const pe_opts* o) {
   return PE_OK;
 }
 
-// Block tile for a call: 256 x 256 (32x32 MFMA fragments, wave tile 128 x 128)
-// halves the LDS and L2 traffic per flop of the 128 x 128 tile, but pads s and
-// L to multiples of 256 and yields 4x fewer tiles.  Used on the bf16 paths when
-// every matrix has s >= 512 and the update has at least one tile per CU.
-// Autotuned choices: shape class -> tile id (1 = 128, 2 = 256), loaded from the
-// text table written by the autotuner.  A class is (precision, s bucket, aspect
-// bucket); see shape_class().
+// Block tile per matrix: 256 x 256 (8 waves, 32x32 MFMA fragments, wave tile
+// 128 x 64) halves the LDS and L2 traffic per flop of the 128 x 128 tile, but
+// pads s and L to multiples of 256 and yields 4x fewer tiles.  The choice comes
+// from the autotuned table, keyed by shape class (precision, s bucket, aspect
+// bucket; see shape_class()) and call regime (_x1 / _xN, see tile_for());
+// without an entry the 256 tile is taken for s >= 512 when the call's update
+// has at least one 256 tile per CU.  FP32 matrices always take the 128 tile.
 std::mutex g_tab_mu;
 std::map<std::string, int> g_tile_table;
 
@@ -316,10 +316,13 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
     d.n_prep = q.prep;
     d.syrk_nt = q.syrk;
     d.upd_nt = q.upd;
-    // split-K: enough Gram-side items to fill the GPU, at least 4 k-stages per split
+    // split-K: enough Gram-side items to fill the GPU, at least 4 k-stages per
+    // split of the Gram; A^2 (k = s, short) splits only with 16 k-stages per
+    // split, since its reduce also runs the combine epilogue (on one 4096 x
+    // 1024 bf16 matrix a two-way A^2 split took 12 us plus 22 us of reduce)
     const int bk = prec == kF32 ? 32 : 64;
     const int max_gram = std::max<int64_t>(1, q.Lp / (4 * bk));
-    const int max_a2 = std::max<int64_t>(1, q.sp / (4 * bk));
+    const int max_a2 = std::max<int64_t>(1, q.sp / (16 * bk));
     const int cap = o->split_k > 0 ? o->split_k : 64;
     d.gram_split = q.syrk ? std::min(std::min(want[q.cls], max_gram), cap) : 1;
     d.a2_split = q.syrk ? std::min(std::min(want[q.cls], max_a2), cap) : 1;

@@ -151,28 +151,33 @@ def test_selection_in_plan_matches_oracle(pe, trained):
 
 def test_learned_plan_large_tile_split_k(pe):
     """The learned path on the 256 tile (8 waves): a 256 x 1024 matrix keeps the
-    raw A^2 epilogue and its moment reduction in the GEMM kernel (no split), a
-    512 x 1024 and a 768 x 1536 matrix take split-K and the reduce kernel.
+    raw A^2 epilogue and its moment reduction in the GEMM kernel (no split of
+    A^2), a 512 x 1024 matrix splits its Gram product, and a 2048 x 2048 matrix
+    splits both, so its raw A^2 epilogue and moment reduction run in the
+    split-K reduce kernel.
     Results equal the plain calls with the forced class's schedule; features
     agree with the oracle's features of the normalised spectrum."""
     import torch
     cases = [(256, 1024, synth.spectrum_powerlaw(256, 1.0)), (512, 1024, np.geomspace(1, 1e-3, 512)),
-             (768, 1536, synth.spectrum_powerlaw(768, 0.7))]
+             (2048, 2048, synth.spectrum_powerlaw(2048, 0.7))]
     Gs, vals = [], []
     for k, (m, n, sig) in enumerate(cases):
         g, v = _materialise(30 + k, m, n, sig)
         Gs.append(g)
         vals.append(v)
     abc4 = OS.greedy_schedule(1e-3, 5).abc
+    # split factor capped at 2 here and in the single calls below: the
+    # automatic factor depends on the call's tile count, and both sides must
+    # sum in the same order
     plan = pe.Plan(Gs, T=5, abc=abc4, compute="bf16", force_class=3, tile=2, out_dtype=torch.float32,
-                   ws_fill=0x5A)
+                   ws_fill=0x5A, split_k=2)
     plan.launch(graph=False)
     torch.cuda.synchronize()
     cls, feats, _, flags = plan.selection()
     assert cls.tolist() == [3, 3, 3] and flags.tolist() == [0, 0, 0]
     T3, abc3 = class_schedule(pe, 3, abc4)
     for k, v in enumerate(vals):
-        Y = pe.polar(Gs[k], T=T3, abc=abc3, compute="bf16", tile=2, out_dtype=torch.float32)
+        Y = pe.polar(Gs[k], T=T3, abc=abc3, compute="bf16", tile=2, out_dtype=torch.float32, split_k=2)
         torch.cuda.synchronize()
         assert relf(to_np(plan.outs[k]), to_np(Y)) <= 1e-6
         s_hat = np.linalg.svd(v / (1.01 * np.linalg.norm(v) + 1e-7), compute_uv=False)

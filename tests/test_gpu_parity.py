@@ -322,12 +322,13 @@ def test_large_tile_bf16_output_equals_rounded_fp32(pe, torch_cuda, shape):
 
 
 @pytest.mark.parametrize("compute", ["bf16", "fp8"])
-@pytest.mark.parametrize("shape", [(768, 2304), (1300, 700)])
+@pytest.mark.parametrize("shape", [(768, 2304), (1300, 700), (2048, 2304)])
 def test_large_tile_unsplit(pe, torch_cuda, shape, compute):
     """split_k = 1 on the 256 tile: off-diagonal Gram and A^2 tiles leave LDS
     through the staged epilogue (mirror rows, then the tile's own rows gathered
     with transposing reads), the path of every Gram and A^2 launch of large
-    batches; the split-K result of the same call agrees to summation order."""
+    batches; the split-K result of the same call agrees to summation order
+    (the Gram splits in every case, A^2 where s >= 2048: 2048 x 2304)."""
     G64 = synth.powerlaw(1400 + shape[0], *shape).G
     G, vals = device_input(G64, torch_cuda.bfloat16)
     abc = oracle_schedule(5)
@@ -376,7 +377,9 @@ def test_mixed_classes_in_one_call(pe, torch_cuda, tmp_path):
     import paper_2505_16932_amd as pkg
     L = pe.lib()
     table = tmp_path / "tiles.txt"
-    table.write_text("bf16_s512_a4_xN 2\nbf16_s1024_a1_xN 1\nbf16_s512_a1_xN 1\n")
+    # entries for both call regimes (this call is small: the one-matrix "_x1" entries apply)
+    table.write_text("".join(f"{c}_{r} {t}\n" for c, t in (("bf16_s512_a4", 2), ("bf16_s1024_a1", 1),
+                                                           ("bf16_s512_a1", 1)) for r in ("x1", "xN")))
     shapes = [(512, 1536), (1024, 1024), (7, 30), (1536, 512), (300, 300)]
     tiles = [2, 1, 1, 2, 1]
     Gs, vals = [], []
