@@ -97,3 +97,58 @@ def test_muon_rejects_fallback_combination(pe):
     with pytest.raises(pe.PEError) as ei:
         pe.polar_batched([G], T=5, moms=[M], muon=(0.9, 0.1, 0.0), force_class=4, fallback_tau=0.1)
     assert ei.value.status == 2
+
+
+def test_muon_with_fast_iteration(pe):
+    """The Muon step on the fast rectangular iteration (FP32, restart 3, no
+    shift): momentum in the norm pass, polar(M) by Algorithm 4, the weight step
+    in the fast path's final update; against the oracle's momentum, its
+    Algorithm 4 on that momentum and the weight step (bar 2e-4, the fast
+    path's own)."""
+    import torch
+    from oracle import fastapply as FA
+    abc = oracle_schedule(5)
+    G, g, M, W = _state((300, 1100), 1530, torch, torch.float32)
+    M0, W0 = to_np(M), to_np(W)
+    lr, beta, wd = 0.5, 0.9, 0.1
+    pe.muon_step([G], [M], [W], lr=lr, beta=beta, wd=wd, T=5, abc=abc, compute="f32",
+                 fast_restart=3, fast_eps=0.0)
+    torch.cuda.synchronize()
+    Mr = beta * M0 + (1.0 - beta) * g
+    Xr = FA.fast_polar_express(Mr, abc, restart=3, eps=0.0)
+    direction = ((1 - lr * wd) * W0 - to_np(W)) / lr
+    em, ex = relf(to_np(M), Mr), relf(direction, Xr)
+    print(f"[muon] fast iteration: momentum relF={em:.2e} direction relF={ex:.3e}", flush=True)
+    assert em <= 1e-6 and ex <= 2e-4
+
+
+@pytest.mark.parametrize("compute,bar", [("f32", 1e-5), ("bf16", 3e-2)])
+def test_muon_with_spectral_init(pe, compute, bar):
+    """The Muon step with the spectrum-aware initialisation (16 power steps)
+    on a momentum with one outlying singular value; against the oracle's
+    momentum, its initialised iteration on that momentum and the weight step
+    (bar: the path's own plus 2e-6 kappa, as for the initialisation alone)."""
+    import torch
+    from oracle import iteration as OI
+    from oracle import spectral_init as SI
+    abc = oracle_schedule(5)
+    r = synth.rng(1540)
+    m, n = 256, 768
+    sig = np.r_[1.0, 0.03 / np.arange(2, m + 1)]
+    G, g = device_input(synth.usv(r, m, n, sig).G, torch.bfloat16)
+    M = torch.zeros((m, n), dtype=torch.float32, device="cuda")
+    W = torch.from_numpy(r.standard_normal((m, n)).astype(np.float32)).cuda()
+    W0 = to_np(W)
+    lr, beta = 1.0, 0.5
+    pe.muon_step([G], [M], [W], lr=lr, beta=beta, T=5, abc=abc, compute=compute, spectral_init=16)
+    torch.cuda.synchronize()
+    Mr = (1.0 - beta) * g
+    Xr = SI.spectrum_aware_polar_express(Mr, abc, iters=16)
+    X0 = OI.normalise(Mr)
+    A = X0 @ X0.T
+    z = SI.power_lower_bound(A, 16)
+    kappa = z * z / max(np.trace(A) - z * z, 1e-300)
+    ex = relf(W0 - to_np(W), Xr)
+    print(f"[muon] spectral init {compute}: direction relF={ex:.3e} kappa={kappa:.1f}", flush=True)
+    assert relf(to_np(M), Mr) <= 1e-6
+    assert ex <= bar + 2e-6 * kappa
