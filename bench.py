@@ -239,9 +239,10 @@ def measured_traffic(workload, compute, tile, fp8_steps):
         return None
 
 
-def cpu_baseline(G_cpu64, abc, T):
-    """The FP64 oracle on the host cores, on one matrix of the workload.
-    Returns the baseline record and the oracle's result."""
+def cpu_baseline(mats, abc, T):
+    """The FP64 oracle on the host cores, on a bounded sample of the workload
+    (the given matrices, about 10-30 s of host work for the wide batch).
+    Returns the baseline record and the oracle's result for the last matrix."""
     from oracle import iteration as OI
     try:
         from threadpoolctl import threadpool_info
@@ -249,40 +250,16 @@ def cpu_baseline(G_cpu64, abc, T):
     except Exception:
         cores = os.cpu_count()
     t0 = time.perf_counter()
-    ref = OI.polar_express(G_cpu64, abc)
+    ref = None
+    for G in mats:
+        ref = OI.polar_express(G, abc)
     dt = time.perf_counter() - t0
-    m, n = G_cpu64.shape
-    fl = algo_flops([(m, n)], T)
+    shapes = [tuple(G.shape) for G in mats]
+    fl = algo_flops(shapes, T)
+    desc = ", ".join(f"{m}x{n}" for m, n in shapes)
     return dict(value=fl / dt / 1e12, unit="TFLOP/s", cores=int(cores), kind="oracle",
                 cpu=cpu_model(),
-                sample=f"1 of the workload's matrices ({m}x{n}), T={T}, FP64 NumPy, {dt:.1f} s"), ref
-
-
-def fast_row(Gs, meta, abc, T, args, stream, torch, log):
-    """The rectangular fast iteration (restart every 3 steps, no shift) against
-    the standard iteration, both FP32, on the three 4096x14336 matrices of the
-    first layer: ms per call and the polar error of every result."""
-    import paper_2505_16932_amd as pe
-    idx = [i for i, G in enumerate(Gs) if max(G.shape) >= 3 * min(G.shape)][:3]
-    sub = [Gs[i] for i in idx]
-    fl = algo_flops([tuple(G.shape) for G in sub], T)
-    row = dict(matrices=len(sub), shape=list(sub[0].shape), T=T, compute="f32", restart=3, eps=0.0)
-    for name, kw in (("standard", {}), ("fast", dict(fast_restart=3, fast_eps=0.0))):
-        plan = pe.Plan(sub, T=T, abc=abc, compute="f32", **kw)
-        ms, _ = time_plan(plan, max(2, min(args.steps, 5)), 1, stream, torch)
-        plan.launch(graph=True)
-        torch.cuda.synchronize()
-        errs = [spec_norm_factored(plan.outs[k], *factors(meta, i), torch) for k, i in enumerate(idx)]
-        row[name] = dict(ms_per_call=round(ms, 3), algorithmic_tflops=round(fl / (ms * 1e-3) / 1e12, 2),
-                         polar_err=[round(e, 5) for e in errs])
-        plan.close()
-        del plan
-        torch.cuda.empty_cache()
-    row["speedup"] = round(row["standard"]["ms_per_call"] / row["fast"]["ms_per_call"], 3)
-    log(f"[bench] fast rectangular iteration (FP32, {len(sub)} x {tuple(sub[0].shape)}): "
-        f"{row['fast']['ms_per_call']} ms against {row['standard']['ms_per_call']} ms "
-        f"(polar error {row['fast']['polar_err']} vs {row['standard']['polar_err']})")
-    return row
+                sample=f"{len(mats)} of the workload's matrices ({desc}), T={T}, FP64 NumPy, {dt:.1f} s"), ref
 
 
 def rel_fro_np(X, ref):
@@ -455,9 +432,13 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        G64 = Gs[ref_idx].to(torch.float64).cpu().numpy()
-        log(f"[bench] cpu oracle on {G64.shape}")
-        cpu, ref = cpu_baseline(G64, abc, T)
+        # the last three matrices (for the wide batch: three 4096x14336, about
+        # 4 s each on 16 host cores); the last one is the relF sample
+        idx = list(range(max(0, len(Gs) - 3), len(Gs)))
+        mats64 = [Gs[i].to(torch.float64).cpu().numpy() for i in idx]
+        G64 = mats64[-1]
+        log(f"[bench] cpu oracle on {len(mats64)} matrices, the last {G64.shape}")
+        cpu, ref = cpu_baseline(mats64, abc, T)
         log(f"[bench] cpu oracle {cpu['value']:.4f} TFLOP/s")
         if samples:
             extra["relF_vs_fp64_oracle"] = {k: float(f"{rel_fro_np(v, ref):.4e}") for k, v in samples.items()}
