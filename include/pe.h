@@ -141,22 +141,28 @@ typedef struct {
                           1: X_0 = G/(||G||_F + 1e-2) (Algorithm 1) */
   int32_t tile;        /* 0 = library choice (autotuned table if loaded), else a
                           tile id from pe_tile_count()/pe_tile_name() */
-  /* Learned choice of l (optional).  With `predictor` (device pointer to
+  /* Learned schedule (optional).  With `predictor` (device pointer to
    * PE_MLP_PARAMS floats, see pe_mlp_*) or force_class >= 0, each matrix runs
-   * one of PE_CLASSES schedules, l = 1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4,
-   * 3e-5 (class 4 uses `abc`, the others pe_coeffs(l, T) with default options),
-   * chosen on the device from tr(A^k), k = 1..4, of the step-1 Gram matrix.
-   * Afterwards ||X X^T - I||_2 is estimated by power iteration; matrices above
+   * one of PE_CLASSES schedules (l, T'): (1e-1, 2), (1e-1, 3), (3e-2, 3),
+   * (1e-2, 4), class 4 = `abc` for all T steps, (3e-3, 4), (3e-4, T),
+   * (1e-4, T), the others from pe_coeffs(l, T) with default options and cut
+   * to min(T', T) steps (a matrix whose schedule has ended skips the later
+   * steps' products; its X passes through).  The class is chosen on the
+   * device from tr(A^k), k = 1..4, of the step-1 Gram matrix.  Afterwards
+   * ||X X^T - I||_2 is estimated by power iteration; matrices above
    * fallback_tau (> 0) that did not run class 4 are recomputed from G with it. */
   const float* predictor;  /* device, PE_MLP_PARAMS floats, or NULL */
   int32_t force_class;     /* -1: the network's choice; 0..7: this class (tests) */
   float fallback_tau;      /* <= 0: no estimate and no fallback */
-  /* Split-K of the two Gram-side products (A = X X^T, A^2).  A launch with
-   * fewer upper-triangle tiles than the device has room for splits each
-   * tile's k range into up to this many partial tiles, summed in split order
-   * by a reduction kernel (deterministic).  0 = library choice (up to 64),
-   * 1 = never split, n in 2..64 = at most n.  Results agree across settings up
-   * to the FP32 summation order.  PE_EINVAL outside 0..64. */
+  /* Split-K of the two Gram-side products (A = X X^T, A^2).  When a launch
+   * has fewer than 64 upper-triangle tiles of a (precision, tile) class, each
+   * tile's k range is split into partial tiles (the Gram keeping at least 4
+   * k-stages per part, A^2 at least 16), summed in split order by a
+   * reduction kernel that runs the epilogue (deterministic).  0 = library
+   * choice (up to 64), 1 = never split, n in 2..64 = at most n.  The
+   * automatic factor depends on the whole call, so a matrix's result agrees
+   * across calls and settings up to the FP32 summation order; with split_k = 1
+   * it is the same bits in any call.  PE_EINVAL outside 0..64. */
   int32_t split_k;
   /* Fast rectangular iteration (Appendix G, Algorithm 4): with fast_restart =
    * k >= 1 the T steps run in segments of k steps, each computing the
@@ -166,7 +172,11 @@ typedef struct {
    * the composite of the ordinary iteration exactly).  FP32 compute only
    * (with bf16 operands the accumulated Q loses the 3e-2 accuracy bar on
    * general spectra), no learned choice of l; PE_EUNSUPPORTED otherwise.
-   * 0 = the ordinary iteration. */
+   * The segment's final X <- q X + D X cancels with q = prod a_t, so its
+   * rounding grows with k: restarts every 3 steps (the paper's choice, q <=
+   * 130 for the l = 1e-3 schedule) keep FP32 within 2e-4 of the FP64
+   * Algorithm 4; k = 5 loses FP32 accuracy altogether.  0 = the ordinary
+   * iteration. */
   int32_t fast_restart;
   float fast_eps;
   /* Muon hyperparameters (used where a pe_matrix carries M or W): momentum
