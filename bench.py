@@ -32,6 +32,10 @@ iteration on the matrix the CPU baseline runs.
 fast_rect_f32 (wide workloads): the rectangular fast iteration (restart every
 3 steps) against the standard iteration, both FP32, on three 4096x14336
 matrices: ms per call and the polar error of each result.
+muon_step, spectral_init, per_head (wide workloads, bf16): the fused Muon
+optimizer step over all matrices, the spectrum-aware initialisation, and the
+first layer's 4096x4096 matrices split into 32 heads of 4096x128, each timed
+against the corresponding plain plan.
 
 Prints ONE JSON line (rank 0, N = 1).
 """
@@ -262,6 +266,97 @@ def cpu_baseline(mats, abc, T):
                 sample=f"{len(mats)} of the workload's matrices ({desc}), T={T}, FP64 NumPy, {dt:.1f} s"), ref
 
 
+def fast_row(Gs, meta, abc, T, args, stream, torch, log):
+    """The rectangular fast iteration (restart every 3 steps, no shift) against
+    the standard iteration, both FP32, on the three 4096x14336 matrices of the
+    first layer: ms per call and the polar error of every result."""
+    import paper_2505_16932_amd as pe
+    idx = [i for i, G in enumerate(Gs) if max(G.shape) >= 3 * min(G.shape)][:3]
+    sub = [Gs[i] for i in idx]
+    fl = algo_flops([tuple(G.shape) for G in sub], T)
+    row = dict(matrices=len(sub), shape=list(sub[0].shape), T=T, compute="f32", restart=3, eps=0.0)
+    for name, kw in (("standard", {}), ("fast", dict(fast_restart=3, fast_eps=0.0))):
+        plan = pe.Plan(sub, T=T, abc=abc, compute="f32", **kw)
+        ms, _ = time_plan(plan, max(2, min(args.steps, 5)), 1, stream, torch)
+        plan.launch(graph=True)
+        torch.cuda.synchronize()
+        errs = [spec_norm_factored(plan.outs[k], *factors(meta, i), torch) for k, i in enumerate(idx)]
+        row[name] = dict(ms_per_call=round(ms, 3), algorithmic_tflops=round(fl / (ms * 1e-3) / 1e12, 2),
+                         polar_err=[round(e, 5) for e in errs])
+        plan.close()
+        del plan
+        torch.cuda.empty_cache()
+    row["speedup"] = round(row["standard"]["ms_per_call"] / row["fast"]["ms_per_call"], 3)
+    log(f"[bench] fast rectangular iteration (FP32, {len(sub)} x {tuple(sub[0].shape)}): "
+        f"{row['fast']['ms_per_call']} ms against {row['standard']['ms_per_call']} ms "
+        f"(polar error {row['fast']['polar_err']} vs {row['standard']['polar_err']})")
+    return row
+
+
+def muon_row(Gs, abc, T, args, stream, torch, log, base_ms):
+    """The fused Muon optimizer step over the whole workload (bf16 weights,
+    FP32 momentum; no X output): ms per step against the plain plan's."""
+    import paper_2505_16932_amd as pe
+    moms = [torch.zeros(G.shape, dtype=torch.float32, device=G.device) for G in Gs]
+    weights = [torch.zeros(G.shape, dtype=torch.bfloat16, device=G.device) for G in Gs]
+    plan = pe.Plan(Gs, outs=[None] * len(Gs), T=T, abc=abc, compute="bf16", moms=moms, weights=weights,
+                   muon=(0.95, 0.02, 0.01))
+    ms, _ = time_plan(plan, max(2, min(args.steps, 5)), 1, stream, torch)
+    plan.close()
+    del plan, moms, weights
+    torch.cuda.empty_cache()
+    log(f"[bench] Muon step (momentum in the norm pass, weight step in the last update): {ms:.3f} ms "
+        f"against {base_ms:.3f} ms for the plain plan")
+    return dict(matrices=len(Gs), beta=0.95, lr=0.02, wd=0.01, weights="bf16", momentum="f32",
+                ms_per_step=round(ms, 3), plain_plan_ms_per_step=round(base_ms, 3),
+                overhead_ms=round(ms - base_ms, 3))
+
+
+def spectral_init_row(Gs, meta, abc, T, args, stream, torch, log, base_ms):
+    """The spectrum-aware initialisation (16 power steps, then the cubic as an
+    extra first step) on the whole workload: ms per step against the plain
+    plan's, and the polar errors of the first layer's results."""
+    import paper_2505_16932_amd as pe
+    plan = pe.Plan(Gs, T=T, abc=abc, compute="bf16", spectral_init=16)
+    ms, _ = time_plan(plan, max(2, min(args.steps, 5)), 1, stream, torch)
+    plan.launch(graph=True)
+    torch.cuda.synchronize()
+    n = min(7, len(Gs))
+    errs = []
+    if "mats" in meta:
+        for k in range(n):
+            errs.append(round(spec_norm_factored(plan.outs[k], *factors(meta, k), torch), 5))
+    plan.close()
+    del plan
+    torch.cuda.empty_cache()
+    log(f"[bench] spectrum-aware init: {ms:.3f} ms against {base_ms:.3f} ms; first-layer polar errors {errs}")
+    return dict(power_steps=16, ms_per_step=round(ms, 3), plain_plan_ms_per_step=round(base_ms, 3),
+                overhead_ms=round(ms - base_ms, 3), polar_err_first_layer=errs)
+
+
+def per_head_row(Gs, abc, T, args, stream, torch, log):
+    """Per-head splitting: the first layer's 4096x4096 matrices, each split into
+    32 column blocks of 4096x128 (views, one grouped call), against the four
+    whole matrices."""
+    import paper_2505_16932_amd as pe
+    sq = [G for G in Gs[:7] if G.shape[0] == G.shape[1]][:4]
+    if not sq:
+        return None
+    heads = [h for G in sq for h in pe.split_heads(G, 32, axis=1)]
+    row = dict(matrices=len(sq), shape=list(sq[0].shape), heads=len(heads), head_shape=list(heads[0].shape))
+    for name, mats in (("whole", sq), ("heads", heads)):
+        plan = pe.Plan(mats, T=T, abc=abc, compute="bf16")
+        ms, _ = time_plan(plan, max(3, min(args.steps, 10)), 1, stream, torch)
+        fl = algo_flops([tuple(m.shape) for m in mats], T)
+        row[name] = dict(ms_per_call=round(ms, 3), algorithmic_tflops=round(fl / (ms * 1e-3) / 1e12, 2))
+        plan.close()
+        del plan
+    torch.cuda.empty_cache()
+    log(f"[bench] per-head split ({len(heads)} x {tuple(heads[0].shape)}): {row['heads']['ms_per_call']} ms "
+        f"against {row['whole']['ms_per_call']} ms for the {len(sq)} whole matrices")
+    return row
+
+
 def rel_fro_np(X, ref):
     import numpy as np
     return float(np.linalg.norm(X - ref) / np.linalg.norm(ref))
@@ -283,6 +378,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fast-row", action="store_true",
                     help="skip the FP32 standard-vs-fast rectangular iteration row")
+    ap.add_argument("--no-extra-rows", action="store_true",
+                    help="skip the Muon, spectrum-aware init and per-head rows")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--phase-reps", type=int, default=10)
     ap.add_argument("--tile", type=int, default=0, help="0 auto, 1 = 128x128, 2 = 256x256 block tile")
@@ -429,6 +526,10 @@ def main():
 
     if args.workload in ("wide-batch", "wide-layer") and not args.no_fast_row and "mats" in meta:
         extra["fast_rect_f32"] = fast_row(Gs, meta, abc, T, args, stream, torch, log)
+    if args.workload in ("wide-batch", "wide-layer") and not args.no_extra_rows and args.compute == "bf16":
+        extra["muon_step"] = muon_row(Gs, abc, T, args, stream, torch, log, ms)
+        extra["spectral_init"] = spectral_init_row(Gs, meta, abc, T, args, stream, torch, log, ms)
+        extra["per_head"] = per_head_row(Gs, abc, T, args, stream, torch, log)
 
     cpu = None
     if not args.no_cpu_baseline:
