@@ -229,19 +229,43 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(KArgs args) {
       for (int j = 0; j < 2; ++j) load8(d, sr0 + rr + 32 * j, sc0 + cc, srn, scn, v[j]);
       if (d.M) {
         // Muon momentum (Section 1.1): M <- beta M + (1 - beta) G in place, and
-        // the iteration runs on the new M (padding stays zero)
+        // the iteration runs on the new M (padding stays zero).  The thread's
+        // 16 values are all loaded before any is stored (16-byte accesses when
+        // the row chunk is inside the matrix and aligned).
+        const bool mvec = ((uintptr_t)d.M % 16 == 0) && (d.ldm % 4 == 0);
+        float mo[2][8];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           const int gr = sr0 + rr + 32 * j;
+          const PE_GLOBAL float* mrow = gview(d.M) + (size_t)gr * d.ldm + sc0 + cc;
+          if (gr < srn && mvec && sc0 + cc + 8 <= scn) {
+            const f32x4 lo = *(const PE_GLOBAL f32x4*)mrow, hi = *(const PE_GLOBAL f32x4*)(mrow + 4);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              mo[j][e] = lo[e];
+              mo[j][e + 4] = hi[e];
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) mo[j][e] = (gr < srn && sc0 + cc + e < scn) ? mrow[e] : 0.0f;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int gr = sr0 + rr + 32 * j;
+          PE_GLOBAL float* mrow = gview_w(d.M) + (size_t)gr * d.ldm + sc0 + cc;
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
-            const int gc = sc0 + cc + e;
-            if (gr < srn && gc < scn) {
-              float* mp = d.M + (size_t)gr * d.ldm + gc;
-              const float mv = __builtin_fmaf(args.mbeta, *mp, (1.0f - args.mbeta) * v[j][e]);
-              *mp = mv;
-              v[j][e] = mv;
-            }
+            mo[j][e] = __builtin_fmaf(args.mbeta, mo[j][e], (1.0f - args.mbeta) * v[j][e]);
+            if (gr < srn && sc0 + cc + e < scn) v[j][e] = mo[j][e];
+          }
+          if (gr < srn && mvec && sc0 + cc + 8 <= scn) {
+            *(PE_GLOBAL f32x4*)mrow = (f32x4){mo[j][0], mo[j][1], mo[j][2], mo[j][3]};
+            *(PE_GLOBAL f32x4*)(mrow + 4) = (f32x4){mo[j][4], mo[j][5], mo[j][6], mo[j][7]};
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              if (gr < srn && sc0 + cc + e < scn) mrow[e] = mo[j][e];
           }
         }
       }
@@ -1426,6 +1450,19 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
             for (int r = 0; r < 4; ++r) *(uint16_t*)(smem + (li + r) * kXtStageRow + ln * 2) = f2bf(v[r]);
           }
         } else if (n < d.L) {
+          // Muon weight step W <- (1 - lr wd) W - lr X_T: the group's four
+          // weights are loaded together, before any of them is stored
+          float wv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+          if (d.W) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              if (i + r < d.s) {
+                const size_t o = d.trans ? (size_t)n * d.ldw + (i + r) : (size_t)(i + r) * d.ldw + n;
+                wv[r] = d.w_bf16 ? bf2f(gview((const uint16_t*)d.W)[o]) : gview((const float*)d.W)[o];
+              }
+            }
+          }
+          const float keep = 1.0f - args.mlr * args.mwd;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             if (i + r < d.s) {
@@ -1435,16 +1472,10 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
                 else st_hint<kStream>((float*)d.Out + o, v[r]);
               }
               if (d.W) {
-                // Muon weight step: W <- (1 - lr wd) W - lr X_T
                 const size_t o = d.trans ? (size_t)n * d.ldw + (i + r) : (size_t)(i + r) * d.ldw + n;
-                const float keep = 1.0f - args.mlr * args.mwd;
-                if (d.w_bf16) {
-                  uint16_t* wp = (uint16_t*)d.W + o;
-                  *wp = f2bf(__builtin_fmaf(-args.mlr, v[r], keep * bf2f(*wp)));
-                } else {
-                  float* wp = (float*)d.W + o;
-                  *wp = __builtin_fmaf(-args.mlr, v[r], keep * *wp);
-                }
+                const float w = __builtin_fmaf(-args.mlr, v[r], keep * wv[r]);
+                if (d.w_bf16) *gview_w((uint16_t*)d.W + o) = f2bf(w);
+                else *gview_w((float*)d.W + o) = w;
               }
             }
           }
