@@ -140,7 +140,8 @@ typedef struct {
   int32_t norm_mode;   /* 0: X_0 = G/(1.01||G||_F + 1e-7) (Appendix A.1 listing);
                           1: X_0 = G/(||G||_F + 1e-2) (Algorithm 1) */
   int32_t tile;        /* 0 = library choice (autotuned table if loaded), else a
-                          tile id from pe_tile_count()/pe_tile_name() */
+                          tile id from pe_tile_count()/pe_tile_name(): 1 the
+                          128 tile, 2 the 256 tile; other values PE_EINVAL */
   /* Learned schedule (optional).  With `predictor` (device pointer to
    * PE_MLP_PARAMS floats, see pe_mlp_*) or force_class >= 0, each matrix runs
    * one of PE_CLASSES schedules (l, T'): (1e-1, 2), (1e-1, 3), (3e-2, 3),

@@ -1373,8 +1373,10 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
   typedef WaveCfg<P, BT> W;
   static_assert(FN == W::FN, "accumulator grid");
   // the last step stages a bf16 output tile the same way, in the caller's
-  // orientation, and stores whole rows (ragged edges element by element)
-  const bool stage_out = LAST && P != kF32 && BT == 256 && d.out_bf16 && d.Out && !d.W;
+  // orientation, and stores whole rows (ragged edges element by element); the
+  // Muon weight step then reads and writes W by whole rows too, from the
+  // staged bf16 X (the values a bf16 output holds)
+  const bool stage_out = LAST && P != kF32 && BT == 256 && (d.Out ? d.out_bf16 != 0 : d.W != nullptr);
   // Streaming loads and stores on the 256 tile, which serves matrices whose
   // iterates are far larger than the caches: its outputs are read by later
   // launches only, and streaming keeps the L2 for the operand panels.  The 128
@@ -1490,16 +1492,88 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
     const int row0 = d.trans ? tn * BT : tm * BT, col0 = d.trans ? tm * BT : tn * BT;
     const int rows = d.trans ? d.L : d.s, cols = d.trans ? d.s : d.L;
     uint16_t* out = (uint16_t*)d.Out;
-    for (int ch = threadIdx.x; ch < 256 * 32; ch += W::NT) {
-      const int r = ch >> 5, c8 = (ch & 31) * 8;
-      const int gr = row0 + r, gc = col0 + c8;
-      if (gr >= rows || gc >= cols) continue;
-      const char* src = smem + r * kXtStageRow + c8 * 2;
-      uint16_t* dst = out + (size_t)gr * d.ldo + gc;
-      if (d.o_vec && gc + 8 <= cols) {
-        st_hint<kStream>((u32x4*)dst, *(const u32x4*)src);
-      } else {
-        for (int e = 0; e < 8 && gc + e < cols; ++e) st_hint<kStream>(dst + e, ((const uint16_t*)src)[e]);
+    const float keep = 1.0f - args.mlr * args.mwd;
+    const bool w_vec = ((uintptr_t)d.W % 16 == 0) && (d.ldw % (d.w_bf16 ? 8 : 4) == 0);
+    // each thread takes kGrp chunks of 8 row elements at a time: the group's
+    // weights are all loaded before any of them is stored
+    constexpr int kGrp = 4;
+    static_assert((256 * 32) % (W::NT * kGrp) == 0, "staged chunks split evenly");
+    for (int c0 = 0; c0 < 256 * 32; c0 += W::NT * kGrp) {
+      float wv[kGrp][8];
+      if (d.W) {
+#pragma unroll
+        for (int q = 0; q < kGrp; ++q) {
+          const int ch = c0 + q * W::NT + threadIdx.x;
+          const int gr = row0 + (ch >> 5), gc = col0 + (ch & 31) * 8;
+          const size_t o = (size_t)gr * d.ldw + gc;
+          if (gr < rows && gc + 8 <= cols && w_vec) {
+            if (d.w_bf16) {
+              const u32x4 raw = *(const PE_GLOBAL u32x4*)(gview((const uint16_t*)d.W) + o);
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                wv[q][2 * e] = bf2f((uint16_t)(raw[e] & 0xffffu));
+                wv[q][2 * e + 1] = bf2f((uint16_t)(raw[e] >> 16));
+              }
+            } else {
+              const PE_GLOBAL f32x4* wq = (const PE_GLOBAL f32x4*)(gview((const float*)d.W) + o);
+              const f32x4 lo = wq[0], hi = wq[1];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                wv[q][e] = lo[e];
+                wv[q][e + 4] = hi[e];
+              }
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              wv[q][e] = 0.0f;
+              if (gr < rows && gc + e < cols)
+                wv[q][e] = d.w_bf16 ? bf2f(gview((const uint16_t*)d.W)[o + e]) : gview((const float*)d.W)[o + e];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kGrp; ++q) {
+        const int ch = c0 + q * W::NT + threadIdx.x;
+        const int r = ch >> 5, c8 = (ch & 31) * 8;
+        const int gr = row0 + r, gc = col0 + c8;
+        if (gr >= rows || gc >= cols) continue;
+        const u32x4 xs = *(const u32x4*)(smem + r * kXtStageRow + c8 * 2);
+        if (d.Out) {
+          uint16_t* dst = out + (size_t)gr * d.ldo + gc;
+          if (d.o_vec && gc + 8 <= cols) {
+            st_hint<kStream>((u32x4*)dst, xs);
+          } else {
+            for (int e = 0; e < 8 && gc + e < cols; ++e)
+              st_hint<kStream>(dst + e, (uint16_t)(xs[e >> 1] >> (16 * (e & 1))));
+          }
+        }
+        if (d.W) {
+          // Muon weight step W <- (1 - lr wd) W - lr X_T
+          float w[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            w[e] = __builtin_fmaf(-args.mlr, bf2f((uint16_t)(xs[e >> 1] >> (16 * (e & 1)))), keep * wv[q][e]);
+          const size_t o = (size_t)gr * d.ldw + gc;
+          if (gc + 8 <= cols && w_vec) {
+            if (d.w_bf16) {
+              u32x4 pk;
+#pragma unroll
+              for (int e = 0; e < 4; ++e) pk[e] = (uint32_t)f2bf(w[2 * e]) | ((uint32_t)f2bf(w[2 * e + 1]) << 16);
+              *(PE_GLOBAL u32x4*)(gview_w((uint16_t*)d.W) + o) = pk;
+            } else {
+              PE_GLOBAL f32x4* wq = (PE_GLOBAL f32x4*)(gview_w((float*)d.W) + o);
+              wq[0] = (f32x4){w[0], w[1], w[2], w[3]};
+              wq[1] = (f32x4){w[4], w[5], w[6], w[7]};
+            }
+          } else {
+            for (int e = 0; e < 8 && gc + e < cols; ++e) {
+              if (d.w_bf16) gview_w((uint16_t*)d.W)[o + e] = f2bf(w[e]);
+              else gview_w((float*)d.W)[o + e] = w[e];
+            }
+          }
+        }
       }
     }
   }

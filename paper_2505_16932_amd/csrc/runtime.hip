@@ -138,6 +138,7 @@ pe_status check_opts(const pe_opts* o) {
   if (o->T < 1 || o->T > kMaxSteps || !o->abc) return PE_EINVAL;
   if (o->compute < PE_COMPUTE_F32 || o->compute > PE_COMPUTE_FP8) return PE_EINVAL;
   if (o->norm_mode != 0 && o->norm_mode != 1) return PE_EINVAL;
+  if (o->tile < 0 || o->tile > 2) return PE_EINVAL;
   if (o->compute == PE_COMPUTE_FP8) {
     if (o->fp8_steps < 0 || o->fp8_steps > o->T - 1) return PE_EINVAL;
   }

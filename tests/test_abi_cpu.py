@@ -106,6 +106,13 @@ def test_workspace_and_argument_checks():
         assert L.pe_polar(ctypes.byref(b), ctypes.byref(o), None, 0, None) == 1
     o2, keep2 = _opts(T=0)
     assert L.pe_polar(ctypes.byref(m), ctypes.byref(o2), None, 0, None) == 1
+    # tile ids: 0 (library choice), 1 (128), 2 (256); anything else is rejected
+    for t, ok in ((0, True), (1, True), (2, True), (3, False), (128, False), (256, False), (-1, False)):
+        o3, keep3 = _opts()
+        o3.tile = t
+        assert (L.pe_workspace_size(1, ctypes.byref(m), ctypes.byref(o3)) > 0) == ok
+        if not ok:
+            assert L.pe_polar(ctypes.byref(m), ctypes.byref(o3), None, 0, None) == 1
     # workspace too small or misaligned: rejected before any launch
     assert L.pe_polar(ctypes.byref(m), ctypes.byref(o), None, 0, None) == 4
     assert L.pe_polar(ctypes.byref(m), ctypes.byref(o), ctypes.c_void_p(256), 16, None) == 4

@@ -71,6 +71,49 @@ def test_muon_bf16_weights_and_output(pe):
     assert np.all(d <= 2.0 ** -8 * np.abs(Wr) + 0.02 * 0.05 + 1e-6)
 
 
+@pytest.mark.parametrize("wdtype,with_out", [("bf16", True), ("bf16", False), ("f32", False), ("f32", True)])
+def test_muon_large_tile_staged_weight_step(pe, wdtype, with_out):
+    """The 256 tile's last update stages X_T in LDS and applies the weight step
+    by whole rows (16-byte accesses, ragged edges element by element, a
+    transposed matrix in the caller's layout): the momentum and the step
+    against the oracle; with a bf16 output and no decay, W' is
+    W - lr X_out rounded once, X_out being the output's own bf16 values."""
+    import torch
+    abc = oracle_schedule(5)
+    shapes = [(300, 700), (700, 300), (512, 1024)]
+    wt = torch.bfloat16 if wdtype == "bf16" else torch.float32
+    lr, beta, wd = (0.02, 0.9, 0.0) if with_out else (0.02, 0.95, 0.1)
+    Gs, gv, Ms, Ws = [], [], [], []
+    for k, sh in enumerate(shapes):
+        G, g, M, W = _state(sh, 1560 + k, torch, wt)
+        Gs.append(G); gv.append(g); Ms.append(M); Ws.append(W)
+    M0 = [to_np(M) for M in Ms]
+    W0 = [to_np(W) for W in Ws]
+    outs = [torch.empty(sh, dtype=torch.bfloat16, device="cuda") for sh in shapes] if with_out else None
+    pe.muon_step(Gs, Ms, Ws, lr=lr, beta=beta, wd=wd, T=5, abc=abc, compute="bf16", outs=outs, tile=2)
+    torch.cuda.synchronize()
+    for k, sh in enumerate(shapes):
+        Mr, Xr, Wr = MU.muon_step(gv[k], M0[k], W0[k], abc, lr=lr, beta=beta, wd=wd)
+        assert relf(to_np(Ms[k]), Mr) <= 1e-6
+        Wk = to_np(Ws[k])
+        if wdtype == "f32":
+            ex = relf(((1 - lr * wd) * W0[k] - Wk) / lr, Xr)
+            print(f"[muon] 256 tile {sh} f32 W: direction relF={ex:.3e}", flush=True)
+            assert ex <= 3e-2
+        else:
+            d = np.abs(Wk - Wr)
+            assert np.all(d <= 2.0 ** -8 * np.abs(Wr) + lr * 0.05 + 1e-6)
+        if with_out:
+            Xo = to_np(outs[k])
+            assert relf(Xo, Xr) <= 3e-2
+            # one FP32 fused multiply-add, then the weight's own rounding
+            w32 = (W0[k] - float(np.float32(lr)) * Xo).astype(np.float32)
+            Wexp = torch.from_numpy(w32).to(wt).to(torch.float64).numpy()
+            bad = int(np.count_nonzero(Wk != Wexp))
+            print(f"[muon] 256 tile {sh} {wdtype} W with bf16 output: {bad} weights differ", flush=True)
+            assert bad == 0
+
+
 def test_muon_plan_replays_are_successive_steps(pe):
     """A plan captured with the Muon fields applies one step per launch: two
     launches equal two oracle steps with the same gradient."""
