@@ -114,6 +114,42 @@ def test_muon_large_tile_staged_weight_step(pe, wdtype, with_out):
             assert bad == 0
 
 
+@pytest.mark.parametrize("wdtype", ["bf16", "f32"])
+def test_muon_large_tile_strided_weights(pe, wdtype):
+    """Weights, momentum and output as column views of wider arrays (row pitch
+    1024 or 512 elements, 700 or 300 columns): the staged weight step takes its
+    16-byte path up to the last whole chunk of a row and the element path for
+    the ragged rest, and leaves the columns past the view untouched."""
+    import torch
+    abc = oracle_schedule(5)
+    wt = torch.bfloat16 if wdtype == "bf16" else torch.float32
+    shapes, pitches = [(300, 700), (700, 300)], [1024, 512]
+    lr = 0.02
+    Gs, Ms, Ws, Wbig, outs = [], [], [], [], []
+    W0, Wbig0 = [], []
+    for k, (sh, pitch) in enumerate(zip(shapes, pitches)):
+        G, g, M, W = _state(sh, 1580 + k, torch, wt)
+        big = torch.from_numpy(synth.rng(1590 + k).standard_normal((sh[0], pitch)).astype(np.float32)).to(wt).cuda()
+        big[:, :sh[1]] = W
+        Mbig = torch.zeros((sh[0], pitch), dtype=torch.float32, device="cuda")
+        Mbig[:, :sh[1]] = M
+        Obig = torch.zeros((sh[0], pitch), dtype=torch.bfloat16, device="cuda")
+        Gs.append(G); Ms.append(Mbig[:, :sh[1]]); Ws.append(big[:, :sh[1]]); Wbig.append(big)
+        outs.append(Obig[:, :sh[1]])
+        W0.append(to_np(W)); Wbig0.append(to_np(big))
+    pe.muon_step(Gs, Ms, Ws, lr=lr, beta=0.9, wd=0.0, T=5, abc=abc, compute="bf16", outs=outs, tile=2)
+    torch.cuda.synchronize()
+    for k, sh in enumerate(shapes):
+        Xo = to_np(outs[k])
+        w32 = (W0[k] - float(np.float32(lr)) * Xo).astype(np.float32)
+        Wexp = torch.from_numpy(w32).to(wt).to(torch.float64).numpy()
+        Wk = to_np(Wbig[k])
+        bad = int(np.count_nonzero(Wk[:, :sh[1]] != Wexp))
+        print(f"[muon] strided {wdtype} W {sh} pitch {pitches[k]}: {bad} weights differ", flush=True)
+        assert bad == 0
+        assert np.array_equal(Wk[:, sh[1]:], Wbig0[k][:, sh[1]:])
+
+
 def test_muon_plan_replays_are_successive_steps(pe):
     """A plan captured with the Muon fields applies one step per launch: two
     launches equal two oracle steps with the same gradient."""
