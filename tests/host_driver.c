@@ -9,7 +9,7 @@
 #include <stdlib.h>
 #include <math.h>
 #include "pe.h"
-int main(void) {
+int main(int argc, char** argv) {
   double abc[3 * 64], lu[2 * 65], err; int iters[64];
   int bad = 0;
   for (int T = 1; T <= 64; T *= 2)
@@ -60,8 +60,11 @@ int main(void) {
   o.split_k = 65; if (pe_workspace_size(64, mats, &o) != 0) bad++; o.split_k = 0;
   if (pe_workspace_size(-1, mats, &o) != 0) bad++;
   /* tile table parsing */
-  const char* tab = "/tmp/san/table.txt";
-  FILE* f = fopen(tab, "w"); fprintf(f, "# c\nbf16_s1024_a1_xN 2\nbogus line\nf32_s256_a4_x1 1\n"); fclose(f);
+  char tab[4096];
+  snprintf(tab, sizeof tab, "%s/table.txt", argc > 1 ? argv[1] : ".");
+  FILE* f = fopen(tab, "w");
+  if (!f) { printf("cannot write %s\n", tab); return 1; }
+  fprintf(f, "# c\nbf16_s1024_a1_xN 2\nbogus line\nf32_s256_a4_x1 1\n"); fclose(f);
   pe_tile_table_load(tab);
   pe_tile_table_load("/nonexistent/table");
   /* online entry points refuse a missing workspace before touching the device */

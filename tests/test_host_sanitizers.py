@@ -45,7 +45,7 @@ def test_host_code_under_sanitizers(tmp_path):
           d + "/coeffs.o"] + objs + ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"])
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1", HIP_VISIBLE_DEVICES="")
-    p = subprocess.run([d + "/driver"], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True,
+    p = subprocess.run([d + "/driver", d], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True,
                        env=env, timeout=300)
     print(p.stdout[-2000:])
     assert "Sanitizer" not in p.stdout and "runtime error" not in p.stdout
