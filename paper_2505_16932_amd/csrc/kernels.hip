@@ -111,6 +111,17 @@ __device__ __forceinline__ bool past_schedule(const KArgs& args, const MatDesc& 
   return args.t >= args.sel_steps[cls];
 }
 
+// bf16 operand copies of the iterate (bf16 / e4m3 paths): step t reads X_t
+// from one of the two buffers, in the Gram product and as the k-rows of B X,
+// while its update writes X_{t+1} into the other (every tile of the update
+// reads all of X_t, so it cannot be overwritten in place)
+__device__ __forceinline__ const uint16_t* xb_cur(const KArgs& args, const MatDesc& d) {
+  return (const uint16_t*)((args.t & 1) ? d.Xb1 : d.Xb);
+}
+__device__ __forceinline__ uint16_t* xb_next(const KArgs& args, const MatDesc& d) {
+  return (uint16_t*)((args.t & 1) ? d.Xb : d.Xb1);
+}
+
 __device__ __forceinline__ void step_coef(const KArgs& args, const MatDesc& d, float* a, float* b,
                                           float* c) {
   if (args.init_step) {
@@ -179,22 +190,15 @@ __device__ __forceinline__ void store8_bf16(uint16_t* dst, const float (&v)[8]) 
 }
 
 // row-major X row chunk: fp32 master and (bf16 paths) the bf16 operand copy
+// of X_0 (the first of the two buffers)
 template <int P>
 __device__ __forceinline__ void store_x_chunk(const MatDesc& d, size_t o, const float (&v)[8]) {
   store8_f32<P>(d.Xf + o, v);
   if (P != kF32) store8_bf16((uint16_t*)d.Xb + o, v);
 }
-// Element (n, i) of the bf16 X^T (Lp x sp), k-blocked: the k = i axis in blocks
-// of 32, each block Lp rows of 64 bytes.  The update's operand stage is then one
-// contiguous 16-KB block, and the epilogue's transposed stores fill whole rows.
-__device__ __forceinline__ size_t xt_blk(int n, int i, size_t Lp) {
-  return ((size_t)(i >> 5) * Lp + n) * 32 + (i & 31);
-}
-// X^T chunk (operand of B X): row n, columns i..i+7 (fp32 path: row-major)
-template <int P>
+// X^T chunk, the fp32 path's operand of B X: row n, columns i..i+7
 __device__ __forceinline__ void store_xt_chunk(const MatDesc& d, int n, int i, const float (&v)[8]) {
-  if (P == kF32) store8_f32<P>((float*)d.XT0 + (size_t)n * d.sp + i, v);
-  else store8_bf16((uint16_t*)d.XT0 + xt_blk(n, i, d.Lp), v);
+  store8_f32<kF32>((float*)d.XT0 + (size_t)n * d.sp + i, v);
 }
 
 template <int P>
@@ -269,28 +273,33 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(KArgs args) {
           }
         }
       }
-      if (u > 0) __syncthreads();  // the previous tile's transposed reads are done
+      // a transposed copy of the block goes through LDS: X itself when G is
+      // tall, X^T on the fp32 path (the bf16 paths read X_0 row-major only)
+      const bool transpose = P == kF32 || d.trans;
+      if (transpose && u > 0) __syncthreads();  // the previous tile's transposed reads are done
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int r = rr + 32 * j;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          tile[r][cc + e] = v[j][e];
+          if (transpose) tile[r][cc + e] = v[j][e];
           ss = __builtin_fmaf(v[j][e], v[j][e], ss);
           amax = fmaxf(amax, fabsf(v[j][e]));
         }
         if (!d.trans) store_x_chunk<P>(d, (size_t)(i0 + r) * d.Lp + k0 + cc, v[j]);
-        else store_xt_chunk<P>(d, k0 + r, i0 + cc, v[j]);
+        else if (P == kF32) store_xt_chunk(d, k0 + r, i0 + cc, v[j]);
       }
-      __syncthreads();
+      if (transpose) {
+        __syncthreads();
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int q = rr + 32 * j;
-        float w[8];
+        for (int j = 0; j < 2; ++j) {
+          const int q = rr + 32 * j;
+          float w[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) w[e] = tile[cc + e][q];
-        if (!d.trans) store_xt_chunk<P>(d, k0 + q, i0 + cc, w);
-        else store_x_chunk<P>(d, (size_t)(i0 + q) * d.Lp + k0 + cc, w);
+          for (int e = 0; e < 8; ++e) w[e] = tile[cc + e][q];
+          if (!d.trans) store_xt_chunk(d, k0 + q, i0 + cc, w);
+          else store_x_chunk<P>(d, (size_t)(i0 + q) * d.Lp + k0 + cc, w);
+        }
       }
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -534,17 +543,41 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("" ::: "memory");
 }
 
-// P is row-major (row stride ld); Q has row stride ldQ and kbQ elements between
-// consecutive 32-deep k blocks (row-major: ldQ = ld, kbQ = 32; the k-blocked
-// X^T: ldQ = 32, kbQ = 32 * rows)
+// The update's second operand can also be X itself, row-major with k along
+// its rows (XR): a stage then holds 32 rows of X (k) by BT columns (n), and
+// the fragments are read with transposing LDS reads.  16-byte chunk c of
+// stage row r sits at chunk c ^ xr_swz(r): each transposing read covers four
+// consecutive rows per 16 lanes, and the swizzle puts them on distinct banks.
 template <int BT>
+__device__ __forceinline__ int xr_swz(int r) {
+  return BT == 256 ? (r & 3) << 2 : ((r & 3) | (((r >> 3) & 1) << 2)) << 1;
+}
+
+// P is row-major (row stride ld); Q has row stride ldQ and kbQ elements between
+// consecutive 32-deep k blocks (row-major: ldQ = ld, kbQ = 32).  XR: Q is
+// row-major X, k along its rows (row stride ldQ), already offset to the
+// tile's first column.
+template <int BT, bool XR = false>
 __device__ __forceinline__ void dl_issue_stage(const PE_GLOBAL uint16_t* P, const PE_GLOBAL uint16_t* Q,
                                                int64_t ld, int64_t ldQ, int64_t kbQ, int kofs, char* slot,
                                                int wave, int lane) {
   typedef DlCfg<BT> C;
   static_assert(C::BK == 32, "one k block per stage");
+  if constexpr (XR) {
+    constexpr int CPR = BT / 8;                      // 16-byte chunks per stage row
 #pragma unroll
-  for (int op = 0; op < 2; ++op) {
+    for (int j = 0; j < C::IPW; ++j) {
+      const int blk = wave * C::IPW + j;            // 1-KB block = 64 / CPR rows
+      const int row = blk * (64 / CPR) + lane / CPR;
+      const int lc = (lane % CPR) ^ xr_swz<BT>(row);  // logical chunk this lane fetches
+      const PE_GLOBAL uint16_t* g = Q + (size_t)(kofs + row) * ldQ + lc * 8;
+      __builtin_amdgcn_global_load_lds((const void*)g,
+                                       (__attribute__((address_space(3))) void*)(slot + C::OPB + blk * 1024),
+                                       16, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int op = 0; op < (XR ? 1 : 2); ++op) {
     const PE_GLOBAL uint16_t* base = op == 0 ? P : Q;
     const int64_t rs = op == 0 ? ld : ldQ;
     const int64_t kb = op == 0 ? 32 : kbQ;
@@ -561,11 +594,22 @@ __device__ __forceinline__ void dl_issue_stage(const PE_GLOBAL uint16_t* P, cons
   }
 }
 
-template <int BT, typename A>
+// Transposing read of an XR stage (rows k, BT columns n): with every 16
+// lanes addressing rows r0..r0+3 (lane q: row r0 + q / 4, columns n0 + 4 (q % 4)
+// .. + 3), lane q receives the four k values of column n0 + q.
+template <int BT>
+__device__ __forceinline__ u32x2 xr_read(const char* sB, int r, int nn) {
+  const char* p = sB + r * (BT * 2) + (((nn >> 3) ^ xr_swz<BT>(r)) << 4) + (nn & 4) * 2;
+  return __builtin_bit_cast(u32x2, __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+                                       (__attribute__((address_space(3))) i16x4*)(p)));
+}
+
+template <int BT, typename A, bool XR = false>
 __device__ __forceinline__ void dl_mma_stage(const char* sA, const char* sB, int wm, int wn, int lane,
                                              A (&acc)[4][4]) {
   constexpr int F = BT / 8;
   constexpr int NSUB = F == 16 ? 1 : 2;          // MFMA k-steps per 32-k stage
+  static_assert(!XR || F == 16, "XR stage reads: 128 tile here, 256 tile in dl_read_frags32");
 #pragma unroll
   for (int ks = 0; ks < NSUB; ++ks) {
     u32x4 fa[4], fb[4];
@@ -575,7 +619,15 @@ __device__ __forceinline__ void dl_mma_stage(const char* sA, const char* sB, int
       const int ra = wm * (BT / 2) + f * F + (lane % F);
       const int rb = wn * (BT / 2) + f * F + (lane % F);
       fa[f] = *(const u32x4*)(sA + ra * 64 + dl_swz(ra, lc) * 16);
-      fb[f] = *(const u32x4*)(sB + rb * 64 + dl_swz(rb, lc) * 16);
+      if constexpr (XR) {
+        // 16x16x32: lane l takes k = 8 (l / 16) .. + 7 of column l % 16
+        const int r = 8 * (lane >> 4) + ((lane & 15) >> 2);
+        const int nn = wn * (BT / 2) + f * F + 4 * (lane & 3);
+        const u32x2 lo = xr_read<BT>(sB, r, nn), hi = xr_read<BT>(sB, r + 4, nn);
+        fb[f] = (u32x4){lo[0], lo[1], hi[0], hi[1]};
+      } else {
+        fb[f] = *(const u32x4*)(sB + rb * 64 + dl_swz(rb, lc) * 16);
+      }
     }
 #pragma unroll
     for (int fm = 0; fm < 4; ++fm)
@@ -601,6 +653,7 @@ struct Frags32 {
   u32x4 a[4], b[2];
 };
 
+template <bool XR = false>
 __device__ __forceinline__ void dl_read_frags32(const char* stage, int sub, int wm, int wn, int lane,
                                                 Frags32& f) {
   constexpr int OPB = DlCfg<256>::OPB;
@@ -612,8 +665,17 @@ __device__ __forceinline__ void dl_read_frags32(const char* stage, int sub, int 
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    const int rb = wn * 64 + i * 32 + (lane & 31);
-    f.b[i] = *(const u32x4*)(stage + OPB + rb * 64 + dl_swz(rb, lc) * 16);
+    if constexpr (XR) {
+      // 32x32x16: lane l takes k = 16 sub + 8 (l / 32) .. + 7 of column l % 32
+      // of the fragment, whose columns are 32 wn + 128 i .. (upd_col)
+      const int r = 16 * sub + 8 * (lane >> 5) + ((lane & 15) >> 2);
+      const int nn = wn * 32 + i * 128 + 16 * ((lane >> 4) & 1) + 4 * (lane & 3);
+      const u32x2 lo = xr_read<256>(stage + OPB, r, nn), hi = xr_read<256>(stage + OPB, r + 4, nn);
+      f.b[i] = (u32x4){lo[0], lo[1], hi[0], hi[1]};
+    } else {
+      const int rb = wn * 64 + i * 32 + (lane & 31);
+      f.b[i] = *(const u32x4*)(stage + OPB + rb * 64 + dl_swz(rb, lc) * 16);
+    }
   }
 }
 
@@ -628,8 +690,8 @@ __device__ __forceinline__ void dl_mfma32(const Frags32& f, A (&acc)[4][2]) {
 }
 
 // acc += P[rp0:+BT, k0:k1] * Q[rq0:+BT, k0:k1]^T (bf16), k0 and k1 multiples of 32;
-// Q's layout as for dl_issue_stage
-template <int BT, typename A, int FN>
+// Q's layout as for dl_issue_stage (XR: acc += P[rp0:+BT, k0:k1] * Q[k0:k1, rq0:+BT])
+template <int BT, typename A, int FN, bool XR = false>
 __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
                                                 const uint16_t* __restrict__ Q, int64_t ld, int64_t ldQ,
                                                 int64_t kbQ, int rp0, int rq0, int k0, int k1, char* smem,
@@ -640,7 +702,8 @@ __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / W::WGN, wn = wave % W::WGN;
   const PE_GLOBAL uint16_t* pP = gview(P) + (size_t)rp0 * ld + k0;
-  const PE_GLOBAL uint16_t* pQ = gview(Q) + (size_t)rq0 * ldQ + (size_t)(k0 >> 5) * kbQ;
+  const PE_GLOBAL uint16_t* pQ = XR ? gview(Q) + (size_t)k0 * ldQ + rq0
+                                    : gview(Q) + (size_t)rq0 * ldQ + (size_t)(k0 >> 5) * kbQ;
   const int nk = (k1 - k0) / C::BK;
   // prologue: stages 0..NS-2 in flight (a stage past the end re-reads the last
   // one, which keeps the count of outstanding loads per iteration fixed)
@@ -648,7 +711,7 @@ __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
 #pragma unroll
   for (int s = 0; s < C::NS - 1; ++s) {
     const int ks = s < nk ? s : nk - 1;
-    dl_issue_stage<BT>(pP, pQ, ld, ldQ, kbQ, ks * C::BK, smem + s * C::STB, wave, lane);
+    dl_issue_stage<BT, XR>(pP, pQ, ld, ldQ, kbQ, ks * C::BK, smem + s * C::STB, wave, lane);
   }
   if constexpr (BT == 128) {
     static_assert(W::NW == 4 && FN == 4, "128 tile: 4 waves");
@@ -658,10 +721,10 @@ __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
       lds_barrier();  // everyone's loads of stage kt landed; stage kt-1's slot is free
       {
         const int ks = kt + C::NS - 1 < nk ? kt + C::NS - 1 : nk - 1;
-        dl_issue_stage<BT>(pP, pQ, ld, ldQ, kbQ, ks * C::BK, smem + ((kt + C::NS - 1) % C::NS) * C::STB, wave, lane);
+        dl_issue_stage<BT, XR>(pP, pQ, ld, ldQ, kbQ, ks * C::BK, smem + ((kt + C::NS - 1) % C::NS) * C::STB, wave, lane);
       }
       const char* cur = smem + (kt % C::NS) * C::STB;
-      dl_mma_stage<BT>(cur, cur + C::OPB, wm, wn, lane, acc);
+      dl_mma_stage<BT, A, XR>(cur, cur + C::OPB, wm, wn, lane, acc);
     }
   } else {
     // 256 tile, two 16-deep k-steps per stage, software-pipelined: the
@@ -675,20 +738,21 @@ __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
     wait_vmcnt<(C::NS - 2) * C::LPS>();
     lds_barrier();  // stage 0 visible
     Frags32 f0, f1;
-    dl_read_frags32(smem, 0, wm, wn, lane, f0);
+    dl_read_frags32<XR>(smem, 0, wm, wn, lane, f0);
     wait_lgkm0();
     for (int kt = 0; kt < nk; ++kt) {
       const char* cur = smem + (kt % C::NS) * C::STB;
       __builtin_amdgcn_sched_barrier(0);
-      dl_read_frags32(cur, 1, wm, wn, lane, f1);
+      dl_read_frags32<XR>(cur, 1, wm, wn, lane, f1);
       dl_mfma32(f0, acc);
-      // 6 LDS reads spread over the first 6 of 8 MFMAs
+      // the LDS reads (6, or 8 with transposing reads) spread over the 8 MFMAs
+      constexpr int NRD = XR ? 8 : 6;
 #pragma unroll
-      for (int q = 0; q < 6; ++q) {
+      for (int q = 0; q < NRD; ++q) {
         __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
       }
-      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+      if constexpr (NRD < 8) __builtin_amdgcn_sched_group_barrier(0x008, 8 - NRD, 0);
       __builtin_amdgcn_sched_barrier(0);
       wait_lgkm0();
       // own loads of stage kt+1 landed; after the barrier everyone's have, and
@@ -699,12 +763,12 @@ __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
       __builtin_amdgcn_sched_barrier(0);
       {
         const int ks = kt + C::NS - 1 < nk ? kt + C::NS - 1 : nk - 1;
-        dl_issue_stage<BT>(pP, pQ, ld, ldQ, kbQ, ks * C::BK, smem + ((kt + C::NS - 1) % C::NS) * C::STB, wave, lane);
+        dl_issue_stage<BT, XR>(pP, pQ, ld, ldQ, kbQ, ks * C::BK, smem + ((kt + C::NS - 1) % C::NS) * C::STB, wave, lane);
       }
       const int nx = kt + 1 < nk ? kt + 1 : kt;
-      dl_read_frags32(smem + (nx % C::NS) * C::STB, 0, wm, wn, lane, f0);
+      dl_read_frags32<XR>(smem + (nx % C::NS) * C::STB, 0, wm, wn, lane, f0);
       dl_mfma32(f1, acc);
-      // 4 direct-to-LDS loads and 6 LDS reads spread over the first 6 of 8 MFMAs
+      // 4 direct-to-LDS loads and the LDS reads spread over the 8 MFMAs
       static_assert(C::LPS == 4, "load count per stage");
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -713,11 +777,11 @@ __device__ __forceinline__ void gemm_nt_tile_dl(const uint16_t* __restrict__ P,
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 1);
       }
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 4; q < NRD; ++q) {
         __builtin_amdgcn_sched_group_barrier(0x100, 1, 1);
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 1);
       }
-      __builtin_amdgcn_sched_group_barrier(0x008, 2, 1);
+      if constexpr (NRD < 8) __builtin_amdgcn_sched_group_barrier(0x008, 8 - NRD, 1);
       __builtin_amdgcn_sched_barrier(0);
       wait_lgkm0();
       __builtin_amdgcn_sched_barrier(0);
@@ -1084,6 +1148,15 @@ __device__ __forceinline__ int acc_col(int wn, int fn, int lane) {
   constexpr int F = TileCfg<BT>::F;
   return wn * WaveCfg<P, BT>::WTN + fn * F + (lane % F);
 }
+// Tile column of an update accumulator.  The bf16 256 tile's update spreads a
+// wave's two fragment columns 128 apart (wave wn: columns 32 wn + 128 fn ..):
+// the fragments' transposing reads from the swizzled X stage then differ by a
+// constant offset, which the LDS instructions take as an immediate.
+template <int P, int BT>
+__device__ __forceinline__ int upd_col(int wn, int fn, int lane) {
+  if constexpr (P != kF32 && BT == 256) return wn * 32 + fn * 128 + (lane & 31);
+  else return acc_col<P, BT>(wn, fn, lane);
+}
 
 // The epilogues read one FP32 matrix (A for B = bA + cA^2, X for X = aX + BX)
 // at the accumulator positions and write others, possibly the same buffer.
@@ -1366,7 +1439,11 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
 }
 
 
-template <int P, int BT, bool LAST, typename A, int FN>
+// STAGE (last step only): the bf16 output or the Muon weights go through an
+// LDS tile (stage_out() below); the two last-step forms are separate
+// instantiations, so that each one's loop stays small enough to unroll fully
+// and index the accumulators with constants.
+template <int P, int BT, bool LAST, bool STAGE, typename A, int FN>
 __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, int tm, int tn,
                                            const A (&acc)[4][FN], char* smem) {
   typedef TileCfg<BT> C;
@@ -1376,7 +1453,8 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
   // orientation, and stores whole rows (ragged edges element by element); the
   // Muon weight step then reads and writes W by whole rows too, from the
   // staged bf16 X (the values a bf16 output holds)
-  const bool stage_out = LAST && P != kF32 && BT == 256 && (d.Out ? d.out_bf16 != 0 : d.W != nullptr);
+  constexpr bool stage_out = STAGE;
+  static_assert(!STAGE || (LAST && P != kF32 && BT == 256), "staged output: last step, bf16 256 tile");
   // Streaming loads and stores on the 256 tile, which serves matrices whose
   // iterates are far larger than the caches: its outputs are read by later
   // launches only, and streaming keeps the L2 for the operand panels.  The 128
@@ -1391,7 +1469,8 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
   if (!args.fast && !past_schedule(args, d)) a += d.scal[kScBeta];
   const float alpha = (args.t == 0) ? d.scal[kScScale] : 1.0f;
   const size_t Lp = d.Lp, sp = d.sp;
-  void* XTn = (args.t & 1) ? d.XT0 : d.XT1;
+  void* XTn = (args.t & 1) ? d.XT0 : d.XT1;   // fp32 path
+  uint16_t* Xbn = P != kF32 ? xb_next(args, d) : nullptr;
   float amax = 0.0f;
   if (stage_out) __syncthreads();  // every wave is done with the operand ring
   // FP32 inputs prefetched one piece ahead: 16 values per lane, i.e. one
@@ -1408,7 +1487,7 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
 #pragma unroll
       for (int g = 0; g < C::RG; ++g) {
         const size_t o = (size_t)(tm * BT + acc_row<BT>(wm, fm, g, lane)) * Lp + tn * BT +
-                         acc_col<P, BT>(wn, fn0 + f, lane);
+                         upd_col<P, BT>(wn, fn0 + f, lane);
 #pragma unroll
         for (int r = 0; r < 4; ++r) dst[f][g][r] = load_as_float<kStream>(d.Xf + o + (size_t)r * Lp);
       }
@@ -1424,7 +1503,7 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
 #pragma unroll
       for (int g = 0; g < C::RG; ++g) {
         const int i = tm * BT + acc_row<BT>(wm, fm, g, lane);
-        const int n = tn * BT + acc_col<P, BT>(wn, fn, lane);
+        const int n = tn * BT + upd_col<P, BT>(wn, fn, lane);
         float v[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[r] = alpha * (a * cur[g][r] + acc[fm][fn][4 * g + r]);
@@ -1433,16 +1512,12 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
           for (int r = 0; r < 4; ++r) {
             const size_t o = (size_t)(i + r) * Lp + n;
             st_hint<kStream>(d.Xf + o, v[r]);
-            if (P != kF32) ((uint16_t*)d.Xb)[o] = f2bf(v[r]);
+            if (P != kF32) Xbn[o] = f2bf(v[r]);
             amax = fmaxf(amax, fabsf(v[r]));
           }
-          if constexpr (P == kF32) {
+          if constexpr (P == kF32)
             st_hint<kStream>((f32x4*)((float*)XTn + (size_t)n * sp + i), (f32x4){v[0], v[1], v[2], v[3]});
-          } else {
-            // k-blocked X^T: the four g rows of a fragment fill 32 whole 64-byte rows
-            *(uint2*)((uint16_t*)XTn + xt_blk(n, i, Lp)) = pack4_bf16(v);
-          }
-        } else if (stage_out) {
+        } else if constexpr (STAGE) {
           // tile-local (row, col) in the caller's layout: (i, n), or (n, i) when transposed
           const int li = i - tm * BT, ln = n - tn * BT;
           if (d.trans) {
@@ -1617,17 +1692,23 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
       int tm, tn;
       banded_decode(local, d.nb, d.nbL, &tm, &tn);
       const T* Bop = args.fast ? (const T*)d.fb[args.fp_] : (const T*)d.Bs;
-      const T* XTc = (const T*)((args.t & 1) ? d.XT1 : d.XT0);
       // (the update always runs in bf16; the FP8 instantiation shares the bf16 loop)
-      // X^T is k-blocked on the bf16 paths: rows of 32 k, one block of Lp rows per 32 k
-      // (a matrix past its schedule: no product, the epilogue copies X)
+      // the bf16 paths read X_t itself (row-major, k along its rows), the fp32
+      // path its transpose; a matrix past its schedule: no product, the
+      // epilogue copies X
       if (past) {
       } else if constexpr (DL)
-        gemm_nt_tile_dl<BT>((const uint16_t*)Bop, (const uint16_t*)XTc, d.sp, 32, (int64_t)32 * d.Lp,
-                            tm * BT, tn * BT, 0, d.sp, smem, acc);
+        gemm_nt_tile_dl<BT, Acc, W::FN, true>((const uint16_t*)Bop, xb_cur(args, d), d.sp, d.Lp, 0, tm * BT,
+                                               tn * BT, 0, d.sp, smem, acc);
       else
-        gemm_nt_tile<T, BT>(Bop, XTc, d.sp, tm * BT, tn * BT, 0, d.sp, smem, acc);
-      epi_update<P, BT, KIND == KIND_UPD_LAST>(args, d, tm, tn, acc, smem);
+        gemm_nt_tile<T, BT>(Bop, (const T*)((args.t & 1) ? d.XT1 : d.XT0), d.sp, tm * BT, tn * BT, 0, d.sp,
+                            smem, acc);
+      if constexpr (KIND == KIND_UPD_LAST && P != kF32 && BT == 256) {
+        if (d.Out ? d.out_bf16 != 0 : d.W != nullptr) epi_update<P, BT, true, true>(args, d, tm, tn, acc, smem);
+        else epi_update<P, BT, true, false>(args, d, tm, tn, acc, smem);
+      } else {
+        epi_update<P, BT, KIND == KIND_UPD_LAST, false>(args, d, tm, tn, acc, smem);
+      }
     } else {
       const int split = KIND == KIND_GRAM ? d.gram_split : d.a2_split;
       const int tile = local / split, ksp = local % split;
@@ -1636,7 +1717,7 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
       const T* Op;
       int K;
       if (KIND == KIND_GRAM) {
-        Op = (P == kF32) ? (const T*)d.Xf : (const T*)d.Xb;
+        Op = (P == kF32) ? (const T*)d.Xf : (const T*)xb_cur(args, d);
         K = d.Lp;
       } else {
         Op = (P == kF32) ? (const T*)d.Af : (const T*)d.As;
@@ -1858,7 +1939,7 @@ __global__ __launch_bounds__(kThreads) void quant_kernel(KArgs args) {
     const MatDesc& d = args.descs[mi];
     if (skip_matrix(args, d) || past_schedule(args, d)) continue;
     const size_t base = (size_t)(item - args.offs[mi]) * kChunks * kThreads * 16;
-    const uint16_t* src = (const uint16_t*)(KIND == KIND_GRAM ? d.Xb : d.As);
+    const uint16_t* src = KIND == KIND_GRAM ? xb_cur(args, d) : (const uint16_t*)d.As;
     uint8_t* dst = KIND == KIND_GRAM ? d.Xq : d.Aq;
     const float inv_q = 1.0f / fp8_operand_scale(d, KIND, args.t);
     u32x4 c[kChunks][2];

@@ -8,9 +8,10 @@
 // X <- aX + (bA + cA^2)X, so every kernel runs on the padded shape with no
 // bounds checks; only the input read and the final store see m, n.
 //   Xf      sp x Lp  fp32   master iterate (row-major)
-//   Xb      sp x Lp  bf16   operand copy of X for the Gram product (bf16/fp8 paths)
-//   XT[2]   Lp x sp  bf16 or fp32   X^T operand for B X (ping-pong across steps); the
-//                           bf16 copy is k-blocked: element (n, i) at ((i/32) Lp + n) 32 + i%32
+//   Xb, Xb1 sp x Lp  bf16   operand copies of X_t (bf16/fp8 paths), used in turn:
+//                           step t reads Xb (t even) or Xb1 (t odd) in the Gram
+//                           product and in B X, and its update writes the other
+//   XT[2]   Lp x sp  fp32   X^T operand for B X on the fp32 path (ping-pong across steps)
 //   Af      sp x sp  fp32   A = X X^T (fp32 path only)
 //   As      sp x sp  bf16   A in bf16 on the bf16/fp8 paths, read by A^2 and by
 //                           the bA term of B (fp32 path: Af itself)
@@ -58,6 +59,7 @@ struct MatDesc {
   int32_t out_bf16, nb, nbL, sel;
   float* Xf;
   void* Xb;
+  void* Xb1;
   void* XT0;
   void* XT1;
   float* Af;

@@ -335,9 +335,13 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
       };
       const size_t X = (size_t)q.sp * q.Lp, A = (size_t)q.sp * q.sp;
       d.Xf = (float*)take(X * 4);
-      d.Xb = prec == kF32 ? nullptr : take(X * 2);
-      d.XT0 = take(X * esz);
-      d.XT1 = take(X * esz);
+      if (prec == kF32) {
+        d.XT0 = take(X * 4);
+        d.XT1 = take(X * 4);
+      } else {
+        d.Xb = take(X * 2);
+        d.Xb1 = take(X * 2);
+      }
       // A in FP32 on the fp32 path; the bf16 paths keep only its bf16 copy,
       // which both A^2 and the bA term of the combine read
       // (bf16 paths: an FP32 A only for the spectrum-aware init's power method)

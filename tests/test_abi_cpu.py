@@ -94,9 +94,9 @@ def test_workspace_and_argument_checks():
     m = pe.Matrix(16, 32, 300, 200, 200, 200, 1, 1)
     n1 = L.pe_workspace_size(1, ctypes.byref(m), ctypes.byref(o))
     assert n1 > 0
-    # padded to 256 x 384, bf16 path: X as FP32 master, bf16 copy and two bf16
-    # transposes; A and B in bf16
-    assert n1 >= 256 * 384 * (4 + 2 + 2 + 2) + 256 * 256 * (2 + 2)
+    # padded to 256 x 384, bf16 path: X as FP32 master and two bf16 copies
+    # (X_t and X_{t+1}); A and B in bf16
+    assert n1 >= 256 * 384 * (4 + 2 + 2) + 256 * 256 * (2 + 2)
     bad = [pe.Matrix(16, 32, 300, 200, 100, 200, 1, 1),   # ldg < n
            pe.Matrix(0, 32, 300, 200, 200, 200, 1, 1),    # null G
            pe.Matrix(16, 32, -1, 200, 200, 200, 1, 1),    # negative m
