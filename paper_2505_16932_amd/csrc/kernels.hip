@@ -64,7 +64,8 @@ __device__ __forceinline__ void st_hint(T* p, T v) {
   else *p = v;
 }
 
-enum Kind : int { KIND_GRAM = 0, KIND_A2 = 1, KIND_UPD = 2, KIND_UPD_LAST = 3 };
+// KIND_UPD0: the first update when X_0 is exactly its bf16 copy (MatDesc::x0b)
+enum Kind : int { KIND_GRAM = 0, KIND_A2 = 1, KIND_UPD = 2, KIND_UPD_LAST = 3, KIND_UPD0 = 4 };
 
 // Descriptor pointers are generic; loads through these global-address-space
 // views compile to global_load (not flat_load), which keeps vmcnt/lgkmcnt apart.
@@ -189,11 +190,12 @@ __device__ __forceinline__ void store8_bf16(uint16_t* dst, const float (&v)[8]) 
   st_stream((u32x4*)dst, w);
 }
 
-// row-major X row chunk: fp32 master and (bf16 paths) the bf16 operand copy
-// of X_0 (the first of the two buffers)
+// row-major X row chunk: fp32 master (unless the bf16 copy holds X_0
+// exactly) and (bf16 paths) the bf16 operand copy of X_0 (the first of the
+// two buffers)
 template <int P>
 __device__ __forceinline__ void store_x_chunk(const MatDesc& d, size_t o, const float (&v)[8]) {
-  store8_f32<P>(d.Xf + o, v);
+  if (P == kF32 || !d.x0b) store8_f32<P>(d.Xf + o, v);
   if (P != kF32) store8_bf16((uint16_t*)d.Xb + o, v);
 }
 // X^T chunk, the fp32 path's operand of B X: row n, columns i..i+7
@@ -1440,10 +1442,11 @@ __device__ __forceinline__ void epi_syrk(const KArgs& args, const MatDesc& d, in
 
 
 // STAGE (last step only): the bf16 output or the Muon weights go through an
-// LDS tile (stage_out() below); the two last-step forms are separate
-// instantiations, so that each one's loop stays small enough to unroll fully
-// and index the accumulators with constants.
-template <int P, int BT, bool LAST, bool STAGE, typename A, int FN>
+// LDS tile (stage_out below); X0B (first step, MatDesc::x0b): X_0 is read
+// from its exact bf16 copy instead of an FP32 master.  Each form is an
+// instantiation of its own, so that every loop stays small enough to unroll
+// fully and index the accumulators with constants.
+template <int P, int BT, bool LAST, bool STAGE, bool X0B, typename A, int FN>
 __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, int tm, int tn,
                                            const A (&acc)[4][FN], char* smem) {
   typedef TileCfg<BT> C;
@@ -1488,8 +1491,15 @@ __device__ __forceinline__ void epi_update(const KArgs& args, const MatDesc& d, 
       for (int g = 0; g < C::RG; ++g) {
         const size_t o = (size_t)(tm * BT + acc_row<BT>(wm, fm, g, lane)) * Lp + tn * BT +
                          upd_col<P, BT>(wn, fn0 + f, lane);
+        if constexpr (X0B) {
+          // X_0 in bf16, also the operand other tiles are reading: ordinary loads
+          const uint16_t* x0 = xb_cur(args, d);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) dst[f][g][r] = load_as_float<kStream>(d.Xf + o + (size_t)r * Lp);
+          for (int r = 0; r < 4; ++r) dst[f][g][r] = load_as_float<false>(x0 + o + (size_t)r * Lp);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) dst[f][g][r] = load_as_float<kStream>(d.Xf + o + (size_t)r * Lp);
+        }
       }
   };
   load_piece(0, pre[0]);
@@ -1662,14 +1672,14 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
   typedef WaveCfg<P, BT> W;
   typedef typename AccT<C::ACC>::type Acc;
   constexpr int BK = P == kFP8 ? Fp8Cfg<BT>::KQ : (P == kBF16 ? DlCfg<BT>::BK : OpT<float>::kBK);
-  constexpr bool UPD = KIND == KIND_UPD || KIND == KIND_UPD_LAST;
+  constexpr bool UPD = KIND == KIND_UPD || KIND == KIND_UPD_LAST || KIND == KIND_UPD0;
   // direct-to-LDS operand ring (the FP8 instantiations run their updates in bf16)
   constexpr bool DL = P == kBF16 || (P == kFP8 && (BT == 256 || UPD));
   constexpr int LDSB0 = DL ? DlCfg<BT>::LDS : (P == kFP8 ? Fp8Cfg<BT>::LDS : C::LDS);
   // the bf16 256 tile stages a SYRK tile's mirror, or the last step's output
   // tile, in the same buffer
   constexpr bool kStageMirror = P != kF32 && BT == 256;
-  constexpr int LDSB = (BT == 256 && P != kF32 && KIND != KIND_UPD && LDSB0 < kXtStageBytes)
+  constexpr int LDSB = (BT == 256 && P != kF32 && KIND != KIND_UPD && KIND != KIND_UPD0 && LDSB0 < kXtStageBytes)
                            ? kXtStageBytes : LDSB0;
   // SYRK kinds: a small tail past the ring for the epilogue's block reductions
   constexpr int kRedTail = (KIND == KIND_GRAM || KIND == KIND_A2) ? 256 : 0;
@@ -1688,7 +1698,7 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
     for (int fm = 0; fm < 4; ++fm)
 #pragma unroll
       for (int fn = 0; fn < W::FN; ++fn) acc[fm][fn] = Acc{};
-    if constexpr (KIND == KIND_UPD || KIND == KIND_UPD_LAST) {
+    if constexpr (UPD) {
       int tm, tn;
       banded_decode(local, d.nb, d.nbL, &tm, &tn);
       const T* Bop = args.fast ? (const T*)d.fb[args.fp_] : (const T*)d.Bs;
@@ -1704,10 +1714,15 @@ __global__ __launch_bounds__((WaveCfg<P, BT>::NT), (BT == 128 ? 2 : 1)) void gem
         gemm_nt_tile<T, BT>(Bop, (const T*)((args.t & 1) ? d.XT1 : d.XT0), d.sp, tm * BT, tn * BT, 0, d.sp,
                             smem, acc);
       if constexpr (KIND == KIND_UPD_LAST && P != kF32 && BT == 256) {
-        if (d.Out ? d.out_bf16 != 0 : d.W != nullptr) epi_update<P, BT, true, true>(args, d, tm, tn, acc, smem);
-        else epi_update<P, BT, true, false>(args, d, tm, tn, acc, smem);
+        if (d.Out ? d.out_bf16 != 0 : d.W != nullptr)
+          epi_update<P, BT, true, true, false>(args, d, tm, tn, acc, smem);
+        else
+          epi_update<P, BT, true, false, false>(args, d, tm, tn, acc, smem);
+      } else if constexpr (KIND == KIND_UPD0) {
+        static_assert(P != kF32, "X_0 from a bf16 copy: bf16 paths only");
+        epi_update<P, BT, false, false, true>(args, d, tm, tn, acc, smem);
       } else {
-        epi_update<P, BT, KIND == KIND_UPD_LAST, false>(args, d, tm, tn, acc, smem);
+        epi_update<P, BT, KIND == KIND_UPD_LAST, false, false>(args, d, tm, tn, acc, smem);
       }
     } else {
       const int split = KIND == KIND_GRAM ? d.gram_split : d.a2_split;
@@ -2078,6 +2093,7 @@ static void warm_t() {
   resident_blocks(reinterpret_cast<const void*>(gemm_kernel<P, KIND_A2, BT>), nt);
   resident_blocks(reinterpret_cast<const void*>(gemm_kernel<P, KIND_UPD, BT>), nt);
   resident_blocks(reinterpret_cast<const void*>(gemm_kernel<P, KIND_UPD_LAST, BT>), nt);
+  if constexpr (P != kF32) resident_blocks(reinterpret_cast<const void*>(gemm_kernel<P, KIND_UPD0, BT>), nt);
   resident_blocks(reinterpret_cast<const void*>(splitk_reduce_kernel<P, KIND_GRAM, BT>), nt);
   resident_blocks(reinterpret_cast<const void*>(splitk_reduce_kernel<P, KIND_A2, BT>), nt);
 }
@@ -2111,6 +2127,8 @@ static void launch_gemm_t(int kind, const KArgs& a, int cap, hipStream_t st) {
          : kind == KIND_A2   ? gemm_kernel<P, KIND_A2, BT>
          : !a.last           ? gemm_kernel<P, KIND_UPD, BT>
                              : gemm_kernel<P, KIND_UPD_LAST, BT>;
+  if constexpr (P != kF32)
+    if (kind == KIND_UPD && !a.last && a.x0b) k = gemm_kernel<P, KIND_UPD0, BT>;
   constexpr int nt = WaveCfg<P, BT>::NT;
   hipLaunchKernelGGL(k, dim3(grid_for(a.total, cap, k, nt)), dim3(nt), 0, st, a);
 }

@@ -91,7 +91,10 @@ struct MatDesc {
   float* M;
   void* W;
   int64_t ldm, ldw;
-  int32_t w_bf16, pad_;
+  int32_t w_bf16;
+  // 1: X_0 is exactly its bf16 copy (bf16 input, bf16/FP8 compute, no Muon
+  // momentum): the norm pass stores no FP32 X_0 and the first update reads Xb
+  int32_t x0b;
 };
 
 // Roles of MatDesc::fb in the fast rectangular iteration: the segment's R_t
@@ -129,6 +132,7 @@ struct KArgs {
   float mbeta, mlr, mwd; // Muon momentum coefficient, learning rate, weight decay
   int32_t init_step;     // the spectrum-aware init step: (a, b, 0) from scal[kScInitA/B]
   const int32_t* sel_steps;  // [n_sched]: steps T' of each class's schedule (learned path)
+  int32_t x0b;           // first update: every matrix of the call reads X_0 from its bf16 copy
 };
 
 // Spectral shift of the update.  In real arithmetic

@@ -113,6 +113,7 @@ struct Layout {
   size_t bytes = 0;
   size_t descs_off = 0, offs_off = 0, coef_off = 0;
   size_t sel_off = 0;  // learned plans: kSelWords words per matrix (class, flag, features, estimate)
+  bool x0b = false;    // every bf16-path matrix has MatDesc::x0b
 };
 
 // per-matrix selection record of a learned plan, contiguous over the matrices
@@ -309,6 +310,9 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
       const int64_t per16 = d.g_bf16 ? 8 : 4;
       d.g_vec = ((uintptr_t)m.G % 16 == 0) && (m.ldg % per16 == 0);
     }
+    // the first update reads X_0 from its bf16 copy when that copy is exact;
+    // a first update that is also the last (one step) reads the FP32 master
+    d.x0b = prec != kF32 && d.g_bf16 && !m.M && o->T + (o->spectral_init > 0 ? 1 : 0) >= 2;
     d.out_bf16 = m.X && m.x_dtype == PE_BF16;
     d.o_vec = d.out_bf16 && ((uintptr_t)m.X % 16 == 0) && (m.ldx % 8 == 0);
     d.nb = q.nb;
@@ -404,6 +408,15 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
       push_all(PH_EST_A, (q.syrk && learned) ? (t ? rows4 : cols64) : 0);
       push_all(PH_EST_B, (q.syrk && learned) ? (t ? cols64 : rows4) : 0);
     }
+  }
+  // the first update reads X_0 from its bf16 copy only when every bf16-path
+  // matrix of the call can (one kernel per launch, no per-matrix branch)
+  {
+    bool all = true;
+    for (size_t i = 0; i < L->descs.size(); ++i)
+      if (L->prec[i] != kF32 && L->descs[i].syrk_nt > 0) all = all && L->descs[i].x0b;
+    for (auto& d : L->descs) d.x0b = all ? d.x0b : 0;
+    L->x0b = all;
   }
   for (int c = 0; c < kNCls; ++c) {
     // Gram phase in longest-k-first matrix order (stable)
@@ -609,6 +622,7 @@ pe_status enqueue_gemm(const pe_plan* p, int t, int kind, hipStream_t st, int fa
     a.fp8 = q && t < p->fp8_steps;
     a.fp8_next = q && t + 1 < p->fp8_steps;
     a.fallback = fallback;
+    a.x0b = kind == 2 && t == 0 && p->L.x0b;
     // learned path, step 1: A^2 and its moments are kept until the class is chosen
     a.raw_a2 = p->learned && !fallback && t == 0 && kind == 1;
     // Gram-side products of the FP8 steps run the e4m3 kernels; updates stay bf16
