@@ -23,6 +23,10 @@
  *    next synchronisation.
  *  - X must not alias G or the workspace.  Concurrent calls on different
  *    streams must use different workspaces.
+ *  - Non-finite input: a NaN or infinite entry of G makes its ||G||_F, and
+ *    with it the scale of X_0, NaN or zero times infinity, so every entry of
+ *    that matrix's result is NaN.  The calls are asynchronous and report no
+ *    status for it; other matrices of a batched call are not affected.
  */
 #ifndef PE_H
 #define PE_H
