@@ -307,7 +307,8 @@ int32_t pe_tile_count(void);
 const char* pe_tile_name(int32_t tile_id);
 /* Lines "<shape-class>_<regime> <tile-id>" ('#' starts a comment); tile-id 1
  * or 2; regime xN for calls of at least 3e12 algorithmic FLOP per step
- * (sum of 3 s^2 L + s^3), x1 below.  With a table
+ * (sum of 3 s^2 L + s^3) or with more than 1024 update tiles of 256, x1
+ * otherwise.  With a table
  * loaded and opts.tile = 0, each matrix of a call takes its class's tile, and
  * every phase of the call launches once per (precision, tile) class present;
  * matrices whose class is missing take the built-in rule (256 for s >= 512 in

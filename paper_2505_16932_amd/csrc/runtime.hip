@@ -194,9 +194,14 @@ int prec_for(const pe_opts* o, int64_t s) {
 
 // Call regimes of the autotuned table: "xN" for calls with at least
 // kBatchFlops algorithmic FLOP per step (3 s^2 L + s^3 summed over the
-// matrices; the autotuner's batches carry ~1.5e13), "x1" below (its single
-// matrices carry at most ~1.3e12).
+// matrices; the autotuner's batches carry ~3e12 per step) or with more than
+// kBatchTiles update tiles of 256 (four per CU of the 256-CU part: then the
+// 256 tile leaves no CU idle), "x1" below.  A batch of 48 GPT-small matrices
+// (2.2e11 FLOP, 1296 tiles) runs 2.76 ms per call on the 256 tile against
+// 3.00 on the 128 tile, while a single 2048 x 32768 matrix (1024 tiles)
+// keeps the 128 tile (2.13 against 2.35 ms).
 constexpr double kBatchFlops = 3e12;
+constexpr int64_t kBatchTiles = 1024;
 
 // Block tile of one matrix.  Forced by opts.tile; else the autotuned table's
 // entry for the matrix's shape class in the call's regime; else 256 for bf16
@@ -234,7 +239,7 @@ pe_status build_layout(int count, const pe_matrix* mats, const pe_opts* o, char*
     upd256 += round_up(s, kTileLarge) / kTileLarge * (round_up(Lx, kTileLarge) / kTileLarge);
     call_flops += 3.0 * (double)s * s * Lx + (double)s * s * s;
   }
-  const bool batch_regime = call_flops >= kBatchFlops;
+  const bool batch_regime = call_flops >= kBatchFlops || upd256 > kBatchTiles;
   // first pass: precision, tile, shapes and Gram-side tile counts per class
   // (for the split-K choice)
   struct Shape { int64_t s, L, sp, Lp; int nb, nbL, syrk, upd, prep, prec, bt, cls; };
