@@ -8,9 +8,11 @@
 //   prep_kernel   one HBM pass over G: orientation, sum of squares (FP32 per
 //                 lane and item, FP64 fixed-order sum of the items' partials
 //                 => deterministic),
-//                 max |G|, and the unscaled FP32 / bf16 / transposed copies of
-//                 X_0; the scale sigma is folded into step 1's epilogues
-//                 (A_1 = sigma^2 G G^T, X_1 = sigma (a G + B_1 G)).
+//                 max |G|, and the unscaled copies of X_0 (bf16 paths: the bf16
+//                 copy, plus an FP32 master unless the bf16 copy is exact;
+//                 FP32 path: X_0 and X_0^T); the scale sigma is folded into
+//                 step 1's epilogues (A_1 = sigma^2 G G^T, X_1 = sigma (a G +
+//                 B_1 G)).
 //   gemm_kernel   persistent blocks over block tiles of 128 (4 waves, 16x16x32
 //                 MFMA, two blocks per CU) or 256 (8 waves in 2 x 4, 32x32x16
 //                 MFMA, one block per CU); bf16 operands go from HBM straight
@@ -19,18 +21,23 @@
 //                             store (SYRK);
 //                 KIND_A2:    B = b A + c A A^T (A symmetric, so A^2 = A A^T is
 //                             again a SYRK), epilogue re-reads A;
-//                 KIND_UPD:   X = a X + B X with X^T as the K-contiguous
-//                             operand; writes the FP32 master, the bf16 copy
-//                             and the next X^T, or the caller's output on the
-//                             last step.
+//                 KIND_UPD:   X = a X + B X; the bf16 paths read X_t itself
+//                             (k along its rows) with transposing LDS reads,
+//                             the FP32 path reads X^T; writes the FP32 master
+//                             and the other bf16 copy (FP32 path: the next
+//                             X^T), or the caller's output on the last step
+//                             (KIND_UPD_LAST); KIND_UPD0 is the first update
+//                             reading X_0 from its exact bf16 copy.
 //                 In the e4m3 steps the Gram-side products read e4m3 copies
 //                 (quant_kernel) on the 256 tile, or convert bf16 operands
 //                 while staging them on the 128 tile.
 //                 Split-K for the Gram-side products writes partial tiles;
 //                 splitk_reduce_kernel sums them in split order (deterministic)
 //                 and runs the same epilogue.
-// All three GEMMs are "NT": C[i][j] = sum_k P[i][k] Q[j][k] with both operands
-// row-major along k, which is what the MFMA lane layout wants.
+// The Gram-side GEMMs are "NT": C[i][j] = sum_k P[i][k] Q[j][k] with both
+// operands row-major along k, which is what the MFMA lane layout wants; the
+// bf16 update's second operand is row-major along n and is transposed by
+// the LDS reads.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
